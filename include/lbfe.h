@@ -1,0 +1,200 @@
+/*
+ * lbfe.h -- C ABI of the MI355X (gfx950) D3Q27 free-energy lattice Boltzmann
+ * library: the chemical-potential-based free-energy model with generalized
+ * (sixth-order Hermite) equilibria and central-moment MRT collision of
+ * Saito, Baba & Takada, arXiv:2504.03819.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every call returns an int status: LBFE_OK (0) or a negative LBFE_E_*
+ *    code.  No exception, abort or exit crosses this boundary; after an error
+ *    lbfe_last_error(ctx) returns a human-readable reason (a string owned by
+ *    the context, valid until the next call on it).
+ *  - Grids are nx * ny * nz lattice nodes.  Scalar fields are double arrays
+ *    laid out [z][y][x] (x fastest); vector fields are [3][z][y][x]; the
+ *    population state is [27][z][y][x] with direction index
+ *    i = 9 (cx+1) + 3 (cy+1) + (cz+1), rest i = 13, opposite 26 - i.
+ *  - With walls_z = 1 the planes z = 0 and z = nz-1 are solid (halfway
+ *    bounce-back and the wetting boundary of Sec. III C); every other node is
+ *    fluid.  With walls_z = 0 the box is periodic in all three directions.
+ *  - Pointers named *_dev are device pointers (HIP device memory on the
+ *    context's device); all others are host pointers.  Every buffer is owned
+ *    by the caller; the library never allocates or frees device memory: it
+ *    works inside one caller-provided workspace (lbfe_bind_workspace).
+ *  - All device work is enqueued on the HIP stream given to lbfe_create and
+ *    is asynchronous unless a call says it synchronises.  One context per
+ *    stream; calls on one context are not thread-safe.
+ */
+#ifndef LBFE_H
+#define LBFE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define LBFE_OK 0
+#define LBFE_E_INVAL (-1)    /* invalid argument or parameter              */
+#define LBFE_E_NOMEM (-2)    /* workspace missing or smaller than required */
+#define LBFE_E_DEVICE (-3)   /* no usable GPU, or a HIP runtime error      */
+#define LBFE_E_DIVERGED (-4) /* NaN/Inf, or density left the EOS domain    */
+#define LBFE_E_STATE (-5)    /* call out of order (e.g. step before init)  */
+
+/* ---- storage / arithmetic forms -------------------------------------- */
+/* LBFE_FP64        populations stored and collided in double.
+ * LBFE_FP32        populations stored in float, collision and forcing in
+ *                  float; density sums, mu, grad mu and reductions in double.
+ * LBFE_FP16_DEV    populations stored as half-precision deviations from the
+ *                  rest-state weights, (f_i - w_i) / w_i; arithmetic as FP32.
+ * LBFE_FP16_DEV_F0FP32  as FP16_DEV but the rest population is kept in float. */
+#define LBFE_FP64 0
+#define LBFE_FP32 1
+#define LBFE_FP16_DEV 2
+#define LBFE_FP16_DEV_F0FP32 3
+
+/* ---- wetting modes, Eq. (38) ------------------------------------------ */
+#define LBFE_WET_NEUTRAL 0 /* rho(x_s) = rho_ave(x_s)                      */
+#define LBFE_WET_PHI 1     /* rho(x_s) = phi * rho_ave   (theta <= 90 deg) */
+#define LBFE_WET_DELTA 2   /* rho(x_s) = rho_ave - drho  (theta >  90 deg) */
+
+/* ---- field selectors for lbfe_field ------------------------------------ */
+#define LBFE_FIELD_RHO 0 /* density, Eq. (11); solid nodes: Eqs. (37)-(38) */
+#define LBFE_FIELD_U 1   /* velocity (3 comps), Eq. (11) incl. F/2; solid 0 */
+#define LBFE_FIELD_MU 2  /* chemical potential, Eq. (32); solid: Eq. (36)  */
+#define LBFE_FIELD_F 3   /* force (3 comps), Eq. (12); solid 0              */
+#define LBFE_FIELD_Q 4   /* Q200, Q020, Q002 (3 comps), Eq. (27); solid 0   */
+#define LBFE_FIELD_PM 5  /* modified pressure p_m = (1 + mu)/3, Eq. (12)    */
+
+/* Parameters of one simulation (Sec. II B and Sec. III). */
+typedef struct lbfe_params {
+    int64_t nx, ny, nz;  /* lattice size, each >= 1 (nz >= 3 with walls)   */
+    int32_t walls_z;     /* 0 periodic; 1 solid planes z = 0 and z = nz-1  */
+    int32_t precision;   /* LBFE_FP64 / FP32 / FP16_DEV / FP16_DEV_F0FP32  */
+    double a, b, R, T;   /* van der Waals EOS, Eqs. (29)-(32)              */
+    double kappa;        /* interfacial coefficient kappa, Eq. (1)         */
+    double nu;           /* kinematic viscosity; 1/omega_1 = rho nu/p_m+1/2 */
+    double omega[11];    /* relaxation rates omega_0..omega_10, in [0, 2];
+                            omega[1] is ignored (derived per node from nu) */
+    int32_t corr4;       /* 1: fourth-order correction Eq. (28), 0: off    */
+    int32_t wet_mode;    /* LBFE_WET_*                                     */
+    double wet_value;    /* phi (> 0) or drho (>= 0) of Eq. (38)           */
+    double rho_l, rho_v; /* coexistence pair for the wetting window; both 0
+                            means: computed by lbfe_create (Maxwell at T) */
+    int32_t check_every; /* lbfe_step checks the divergence flag every this
+                            many steps (>= 1) and at the end               */
+    int32_t adjoint;     /* 1: the workspace also holds adjoint buffers    */
+} lbfe_params;
+
+typedef struct lbfe_ctx lbfe_ctx;
+
+/* Fill *p with the paper's defaults (Sec. III): a = 9/392, b = 2/21, R = 1,
+ * T = 0.7 T_c, kappa = 0.02, nu = 0.15, all omega_k = 1, corr4 on,
+ * periodic 32^3, neutral wetting, FP64, check_every = 100, adjoint off. */
+int lbfe_params_default(lbfe_params *p);
+
+/* Coexistence pair of the vdW EOS at temperature T from equal chemical
+ * potential and equal pressure (Maxwell's rule, Sec. III).  Host only.
+ * E_INVAL if T is not strictly between 0.3 T_c and T_c. */
+int lbfe_coexistence(double a, double b, double R, double T, double *rho_l, double *rho_v);
+
+/* Validate *p, derive constants (coexistence pair if not given, wetting
+ * window 0.05 rl + 0.95 rv .. 0.95 rl + 0.05 rv) and create a context bound
+ * to the current HIP device and the given stream (hipStream_t as void*;
+ * NULL = default stream).  Allocates no device memory.
+ * E_INVAL on a bad parameter (checked before any device call), E_DEVICE
+ * when no GPU is usable. */
+int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out);
+
+/* Bytes of device workspace a context with these parameters needs. */
+int lbfe_workspace_bytes(const lbfe_params *p, size_t *bytes);
+
+/* Bind caller-owned device memory (256-byte aligned, >= the size from
+ * lbfe_workspace_bytes) as the context's workspace.  The memory must outlive
+ * the context; the library never frees it.  E_NOMEM if too small. */
+int lbfe_bind_workspace(lbfe_ctx *ctx, void *workspace_dev, size_t bytes);
+
+/* Copy the context's parameters, with derived rho_l/rho_v, into *out. */
+int lbfe_get_params(const lbfe_ctx *ctx, lbfe_params *out);
+
+/* Initial state (Sec. III B, Eqs. (34)-(35) give the paper's droplets):
+ * populations at the generalized equilibrium of Eq. (20) with density rho0,
+ * velocity u0 (NULL = 0) and p_m from mu[rho0] (solid-node densities from
+ * Eqs. (37)-(38) first).  rho0_dev: double[nz][ny][nx], entries at solid
+ * nodes are ignored; u0_dev: double[3][nz][ny][nx] or NULL.  Synchronises
+ * once to validate: E_INVAL if a fluid density is not finite or outside the
+ * EOS domain 0 < rho < 1/b.  Resets the step counter to 0. */
+int lbfe_init_density(lbfe_ctx *ctx, const double *rho0_dev, const double *u0_dev);
+
+/* Advance nsteps time steps (Sec. II B): density and momentum, wall density
+ * Eqs. (37)-(38), chemical potential Eq. (32) with Eq. (36) at walls, force
+ * Eq. (12), Q corrections Eqs. (27)-(28), central-moment collision
+ * Eqs. (21)-(26), inverse transform and streaming Eq. (10) with halfway
+ * bounce-back.  Checks the divergence flag every check_every steps and at
+ * the end (a synchronisation): E_DIVERGED, with the step in lbfe_last_error. */
+int lbfe_step(lbfe_ctx *ctx, int64_t nsteps);
+
+/* Number of steps taken since lbfe_init_density / lbfe_set_state. */
+int lbfe_step_count(const lbfe_ctx *ctx, int64_t *step);
+
+/* Macroscopic fields of the current state f(t) (the quantities the next
+ * step would use).  Each pointer may be NULL; rho_dev, mu_dev:
+ * double[nz][ny][nx]; u_dev, F_dev: double[3][nz][ny][nx]. */
+int lbfe_fields(lbfe_ctx *ctx, double *rho_dev, double *u_dev, double *mu_dev, double *F_dev);
+
+/* One field of the current state by selector LBFE_FIELD_*; out_dev holds
+ * 1 or 3 (U, F, Q) double planes of nz*ny*nx. */
+int lbfe_field(lbfe_ctx *ctx, int which, double *out_dev);
+
+/* Size in bytes of the raw population state at storage precision. */
+int lbfe_state_bytes(const lbfe_ctx *ctx, size_t *bytes);
+/* Raw state copy out / in (checkpoints).  set_state also sets the counter. */
+int lbfe_get_state(lbfe_ctx *ctx, void *dst_dev);
+int lbfe_set_state(lbfe_ctx *ctx, const void *src_dev, int64_t step);
+
+/* Populations decoded to / encoded from double[27][nz][ny][nx] (solid-node
+ * entries read as 0 and are ignored on input). */
+int lbfe_get_populations(lbfe_ctx *ctx, double *f_dev);
+int lbfe_set_populations(lbfe_ctx *ctx, const double *f_dev);
+
+/* Deterministic FP64 reductions over fluid nodes of the current state:
+ * out[0] = sum rho, out[1..3] = sum j (= sum_i f_i c_i), out[4..6] = sum F,
+ * out[7] = max |u|.  Host array; synchronises. */
+int lbfe_reduce(lbfe_ctx *ctx, double out[8]);
+
+/* ---- discrete adjoint (needs params.adjoint = 1) ----------------------- *
+ * The adjoint state lambda(t) = dL/df(t) is held in the workspace.  Reverse
+ * sweep: lbfe_adjoint_seed at the final time T, then for t = T-1 .. 0
+ * lbfe_adjoint_step with the forward state f(t) (raw state as returned by
+ * lbfe_get_state), then lbfe_adjoint_init_density for dL/drho0.
+ * lbfe_adjoint_grads returns the accumulated parameter gradients. */
+
+/* lambda(T)_i(x) = dL/drho(x) for every i (rho = sum_i f_i); resets the
+ * parameter-gradient accumulators.  dL_drho_dev: double[nz][ny][nx]. */
+int lbfe_adjoint_seed(lbfe_ctx *ctx, const double *dL_drho_dev);
+
+/* lambda(t) = (d step / d f(t))^T lambda(t+1), accumulating the parameter
+ * gradients; state_t_dev is f(t) at storage precision.  Deterministic. */
+int lbfe_adjoint_step(lbfe_ctx *ctx, const void *state_t_dev);
+
+/* Pull lambda(0) back through the initialiser: dL/drho0 into
+ * dL_drho0_dev (double[nz][ny][nx], zero at solid nodes), and add the
+ * initialiser's kappa / wetting-value contributions to the accumulators. */
+int lbfe_adjoint_init_density(lbfe_ctx *ctx, const double *rho0_dev, double *dL_drho0_dev);
+
+/* out[0] = dL/dkappa, out[1] = dL/d(wet_value), out[2] = dL/dnu,
+ * out[3] reserved (0).  Host array; synchronises. */
+int lbfe_adjoint_grads(lbfe_ctx *ctx, double out[4]);
+
+/* Reason for the last error on this context (never NULL). */
+const char *lbfe_last_error(const lbfe_ctx *ctx);
+
+/* Release the context (not the caller's workspace).  NULL is a no-op. */
+int lbfe_destroy(lbfe_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBFE_H */

@@ -1,0 +1,303 @@
+// Device-side building blocks of the D3Q27 free-energy LB step (gfx950):
+// precision policies, population storage codecs, neighbour indexing, the
+// factorised central-moment transform, the collision of Eqs. (21)-(26) and
+// the discrete operators.  Included by the forward and adjoint kernel files.
+#pragma once
+
+#include "lbfe_internal.h"
+
+namespace lbfe {
+
+// ---------------------------------------------------------------------------
+// Lattice.  Direction i = 9 (cx+1) + 3 (cy+1) + (cz+1).  The D3Q27 weights of
+// Eq. (17) are products of the D1Q3 weights 1/6, 2/3, 1/6.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr double w1(int c) { return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0; }
+__host__ __device__ constexpr double wq(int cx, int cy, int cz) { return w1(cx) * w1(cy) * w1(cz); }
+__host__ __device__ constexpr int cxi(int i) { return i / 9 - 1; }
+__host__ __device__ constexpr int cyi(int i) { return (i / 3) % 3 - 1; }
+__host__ __device__ constexpr int czi(int i) { return i % 3 - 1; }
+__host__ __device__ constexpr double wi(int i) { return wq(cxi(i), cyi(i), czi(i)); }
+constexpr int kRest = 13;
+
+// Central-moment slot of k_{abg} after the factorised transform.
+__host__ __device__ constexpr int K(int a, int b, int g) { return 9 * a + 3 * b + g; }
+
+// ---------------------------------------------------------------------------
+// Precision policies and population storage
+// ---------------------------------------------------------------------------
+template <int P> struct Pol { using real = float; };
+template <> struct Pol<LBFE_FP64> { using real = double; };
+
+template <int P> struct Pops;
+
+template <> struct Pops<LBFE_FP64> {
+    double *p;
+    unsigned N;
+    __device__ Pops(const void *q, unsigned n) : p((double *)q), N(n) {}
+    __device__ double ld(int i, unsigned n) const { return p[(size_t)i * N + n]; }
+    __device__ void st(int i, unsigned n, double v) const { p[(size_t)i * N + n] = v; }
+};
+
+template <> struct Pops<LBFE_FP32> {
+    float *p;
+    unsigned N;
+    __device__ Pops(const void *q, unsigned n) : p((float *)q), N(n) {}
+    __device__ float ld(int i, unsigned n) const { return p[(size_t)i * N + n]; }
+    __device__ void st(int i, unsigned n, float v) const { p[(size_t)i * N + n] = v; }
+};
+
+// Half-precision deviation from the rest-state weight, scaled by the weight:
+// stored h_i = (f_i - w_i) / w_i, decoded f_i = w_i (1 + h_i).  The scale
+// keeps the small deviations of the moving populations away from the half
+// subnormal range.
+__device__ inline float dec16(int i, __half h) {
+    const float w = (float)wi(i);
+    return fmaf(w, __half2float(h), w);
+}
+__device__ inline __half enc16(int i, float f) {
+    const float iw = (float)(1.0 / wi(i));
+    return __float2half_rn(fmaf(f, iw, -1.0f));
+}
+
+template <> struct Pops<LBFE_FP16_DEV> {
+    __half *p;
+    unsigned N;
+    __device__ Pops(const void *q, unsigned n) : p((__half *)q), N(n) {}
+    __device__ float ld(int i, unsigned n) const { return dec16(i, p[(size_t)i * N + n]); }
+    __device__ void st(int i, unsigned n, float v) const { p[(size_t)i * N + n] = enc16(i, v); }
+};
+
+// Rest population in float, the 26 moving ones as half deviations.
+template <> struct Pops<LBFE_FP16_DEV_F0FP32> {
+    __half *p;
+    float *p0;
+    unsigned N;
+    __device__ Pops(const void *q, unsigned n)
+        : p((__half *)q), p0((float *)((char *)q + ((26 * 2 * (size_t)n + 255) & ~size_t(255)))), N(n) {}
+    __device__ static int slot(int i) { return i < kRest ? i : i - 1; }
+    __device__ float ld(int i, unsigned n) const {
+        return i == kRest ? p0[n] : dec16(i, p[(size_t)slot(i) * N + n]);
+    }
+    __device__ void st(int i, unsigned n, float v) const {
+        if (i == kRest)
+            p0[n] = v;
+        else
+            p[(size_t)slot(i) * N + n] = enc16(i, v);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Work mapping.  Workgroups are handed to the 8 XCDs round-robin; with
+// xcd_remap the tile index is permuted so that every XCD owns one
+// contiguous range of tiles (neighbouring rows share that XCD's L2).
+// ---------------------------------------------------------------------------
+__device__ inline unsigned tile_id(const KP &kp) {
+    const unsigned b = blockIdx.x, nb = gridDim.x;
+    if (!kp.xcd_remap) return b;
+    const unsigned q = nb >> 3, r = nb & 7u, k = b & 7u;
+    return k * q + (k < r ? k : r) + (b >> 3);
+}
+
+// Neighbour offsets of node (x, y, z) with periodic wrap.
+struct Nb {
+    unsigned X[3], Y[3], Z[3];
+    __device__ Nb(const KP &kp, int x, int y, int z) {
+        X[0] = x == 0 ? kp.nx - 1 : x - 1;
+        X[1] = x;
+        X[2] = x == kp.nx - 1 ? 0 : x + 1;
+        Y[0] = (y == 0 ? kp.ny - 1 : y - 1) * (unsigned)kp.nx;
+        Y[1] = y * (unsigned)kp.nx;
+        Y[2] = (y == kp.ny - 1 ? 0 : y + 1) * (unsigned)kp.nx;
+        Z[0] = (z == 0 ? kp.nz - 1 : z - 1) * kp.plane;
+        Z[1] = z * kp.plane;
+        Z[2] = (z == kp.nz - 1 ? 0 : z + 1) * kp.plane;
+    }
+    __device__ unsigned at(int cx, int cy, int cz) const { return X[cx + 1] + Y[cy + 1] + Z[cz + 1]; }
+};
+
+__device__ inline void decompose(const KP &kp, unsigned n, int &x, int &y, int &z) {
+    z = (int)(n / kp.plane);
+    const unsigned r = n - (unsigned)z * kp.plane;
+    y = (int)(r / (unsigned)kp.nx);
+    x = (int)(r - (unsigned)y * (unsigned)kp.nx);
+}
+
+// ---------------------------------------------------------------------------
+// Macroscopic moments, Eq. (11): rho = sum f (accumulated in double),
+// j = sum f c.
+// ---------------------------------------------------------------------------
+template <class real>
+__device__ inline void moments(const real (&f)[27], double &rho, real &jx, real &jy, real &jz) {
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) r += (double)f[i];
+    rho = r;
+    real px = 0, mx = 0, py = 0, my = 0, pz = 0, mz = 0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        if (cxi(i) > 0) px += f[i];
+        if (cxi(i) < 0) mx += f[i];
+        if (cyi(i) > 0) py += f[i];
+        if (cyi(i) < 0) my += f[i];
+        if (czi(i) > 0) pz += f[i];
+        if (czi(i) < 0) mz += f[i];
+    }
+    jx = px - mx;
+    jy = py - my;
+    jz = pz - mz;
+}
+
+// Bulk chemical potential of the vdW fluid, Eq. (32) without the kappa term.
+__device__ inline double mu_bulk(const KP &kp, double r) {
+    const double d = 1.0 - kp.b * r;
+    return kp.RT * (log(r / d) + 1.0 / d) - 2.0 * kp.a * r;
+}
+
+// Q_aa = -3 d_a phi_a (Eq. (27)) with the isotropic gradient
+// d_a g = 3 sum_i w_i c_ia g(x + c_i); for the a-component only the 18
+// neighbours with c_a != 0 contribute: d_x g = 1/2 sum_{cy,cz} w(cy) w(cz)
+// [g(x+1,..) - g(x-1,..)].
+template <class real>
+__device__ inline void q_terms(const KP &kp, const Nb &nb, const real *phi, real &q200, real &q020, real &q002) {
+    const real *px = phi, *py = phi + kp.N, *pz = phi + 2 * (size_t)kp.N;
+    real sx = 0, sy = 0, sz = 0;
+#pragma unroll
+    for (int a = -1; a <= 1; ++a)
+#pragma unroll
+        for (int b = -1; b <= 1; ++b) {
+            const real w = (real)(w1(a) * w1(b));
+            sx += w * (px[nb.at(1, a, b)] - px[nb.at(-1, a, b)]);
+            sy += w * (py[nb.at(a, 1, b)] - py[nb.at(a, -1, b)]);
+            sz += w * (pz[nb.at(a, b, 1)] - pz[nb.at(a, b, -1)]);
+        }
+    q200 = (real)(-1.5) * sx;
+    q020 = (real)(-1.5) * sy;
+    q002 = (real)(-1.5) * sz;
+}
+
+// ---------------------------------------------------------------------------
+// Factorised central-moment transform (Eq. (19)).  Along one axis with
+// velocity component u, the triple (f-, f0, f+) maps to the 1-D central
+// moments (k0, k1, k2) = sum f (c - u)^n; the 3-D transform is three such
+// passes (z, y, x).  After the passes slot K(a,b,g) holds k_{abg}.
+// ---------------------------------------------------------------------------
+template <class real> __device__ inline void fwd3(real &fm, real &f0, real &fp, real u) {
+    const real s = fp + fm, d = fp - fm;
+    const real k0 = s + f0;
+    const real k1 = d - u * k0;
+    const real k2 = s - (real)2 * u * d + u * u * k0;
+    fm = k0;
+    f0 = k1;
+    fp = k2;
+}
+template <class real> __device__ inline void inv3(real &a, real &b, real &c, real u) {
+    const real k0 = a, k1 = b, k2 = c;
+    const real m1 = k1 + u * k0;
+    const real m2 = k2 + (real)2 * u * k1 + u * u * k0;
+    a = (real)0.5 * (m2 - m1);
+    b = k0 - m2;
+    c = (real)0.5 * (m2 + m1);
+}
+
+template <class real> __device__ inline void cm_forward(real (&f)[27], real ux, real uy, real uz) {
+#pragma unroll
+    for (int p = 0; p < 9; ++p) fwd3(f[3 * p], f[3 * p + 1], f[3 * p + 2], uz);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int g = 0; g < 3; ++g) fwd3(f[9 * a + g], f[9 * a + 3 + g], f[9 * a + 6 + g], uy);
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int g = 0; g < 3; ++g) fwd3(f[3 * b + g], f[9 + 3 * b + g], f[18 + 3 * b + g], ux);
+}
+
+template <class real> __device__ inline void cm_inverse(real (&f)[27], real ux, real uy, real uz) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int g = 0; g < 3; ++g) inv3(f[3 * b + g], f[9 + 3 * b + g], f[18 + 3 * b + g], ux);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int g = 0; g < 3; ++g) inv3(f[9 * a + g], f[9 * a + 3 + g], f[9 * a + 6 + g], uy);
+#pragma unroll
+    for (int p = 0; p < 9; ++p) inv3(f[3 * p], f[3 * p + 1], f[3 * p + 2], uz);
+}
+
+// ---------------------------------------------------------------------------
+// Collision in central-moment space, Eqs. (21)-(26), toward the equilibria of
+// Eq. (20).  The combination equations of each order are solved in closed
+// form.  om: the 11 rates with om[1] replaced by the local omega_1.
+// ---------------------------------------------------------------------------
+template <class real> struct Rates {
+    real w[11];
+};
+
+template <class real>
+__device__ inline void collide(real (&k)[27], const Rates<real> &R, real Fx, real Fy, real Fz, real pm, real q200,
+                               real q020, real q002, real q220, real q202, real q022) {
+    const real one = 1, half = 0.5, third = (real)(1.0 / 3.0), ninth = (real)(1.0 / 9.0);
+    const real *w = R.w;
+    // first order, Eq. (21)
+    k[K(1, 0, 0)] = (one - w[0]) * k[K(1, 0, 0)] + (one - half * w[0]) * Fx;
+    k[K(0, 1, 0)] = (one - w[0]) * k[K(0, 1, 0)] + (one - half * w[0]) * Fy;
+    k[K(0, 0, 1)] = (one - w[0]) * k[K(0, 0, 1)] + (one - half * w[0]) * Fz;
+    // second order, Eq. (22)
+    k[K(1, 1, 0)] *= (one - w[1]);
+    k[K(0, 1, 1)] *= (one - w[1]);
+    k[K(1, 0, 1)] *= (one - w[1]);
+    {
+        const real k200 = k[K(2, 0, 0)], k020 = k[K(0, 2, 0)], k002 = k[K(0, 0, 2)];
+        const real A = (one - w[1]) * (k200 - k020) + (one - half * w[1]) * (q200 - q020);
+        const real B = (one - w[1]) * (k200 - k002) + (one - half * w[1]) * (q200 - q002);
+        const real S = (one - w[2]) * (k200 + k020 + k002) + (real)3 * w[2] * pm +
+                       (one - half * w[2]) * (q200 + q020 + q002);
+        k[K(2, 0, 0)] = third * (S + A + B);
+        k[K(0, 2, 0)] = third * (S - (real)2 * A + B);
+        k[K(0, 0, 2)] = third * (S + A - (real)2 * B);
+    }
+    // third order, Eq. (23)
+    {
+        const real c3 = (one - half * w[3]) * (real)(2.0 / 3.0), r4 = one - w[4], r3 = one - w[3];
+        real P, M;
+        P = r3 * (k[K(1, 2, 0)] + k[K(1, 0, 2)]) + c3 * Fx;
+        M = r4 * (k[K(1, 2, 0)] - k[K(1, 0, 2)]);
+        k[K(1, 2, 0)] = half * (P + M);
+        k[K(1, 0, 2)] = half * (P - M);
+        P = r3 * (k[K(2, 1, 0)] + k[K(0, 1, 2)]) + c3 * Fy;
+        M = r4 * (k[K(2, 1, 0)] - k[K(0, 1, 2)]);
+        k[K(2, 1, 0)] = half * (P + M);
+        k[K(0, 1, 2)] = half * (P - M);
+        P = r3 * (k[K(2, 0, 1)] + k[K(0, 2, 1)]) + c3 * Fz;
+        M = r4 * (k[K(2, 0, 1)] - k[K(0, 2, 1)]);
+        k[K(2, 0, 1)] = half * (P + M);
+        k[K(0, 2, 1)] = half * (P - M);
+        k[K(1, 1, 1)] *= (one - w[5]);
+    }
+    // fourth order, Eq. (24)
+    {
+        const real k220 = k[K(2, 2, 0)], k202 = k[K(2, 0, 2)], k022 = k[K(0, 2, 2)];
+        const real D1 = (one - w[6]) * (k220 - (real)2 * k202 + k022) + (one - half * w[6]) * (q220 - (real)2 * q202 + q022);
+        const real D2 = (one - w[6]) * (k220 + k202 - (real)2 * k022) + (one - half * w[6]) * (q220 + q202 - (real)2 * q022);
+        const real S4 = (one - w[7]) * (k220 + k202 + k022) + w[7] * pm + (one - half * w[7]) * (q220 + q202 + q022);
+        k[K(2, 2, 0)] = third * (S4 + D1 + D2);
+        k[K(2, 0, 2)] = third * (S4 - D1);
+        k[K(0, 2, 2)] = third * (S4 - D2);
+        k[K(2, 1, 1)] *= (one - w[8]);
+        k[K(1, 2, 1)] *= (one - w[8]);
+        k[K(1, 1, 2)] *= (one - w[8]);
+    }
+    // fifth order, Eq. (25)
+    {
+        const real c9 = (one - half * w[9]) * ninth, r9 = one - w[9];
+        k[K(1, 2, 2)] = r9 * k[K(1, 2, 2)] + c9 * Fx;
+        k[K(2, 1, 2)] = r9 * k[K(2, 1, 2)] + c9 * Fy;
+        k[K(2, 2, 1)] = r9 * k[K(2, 2, 1)] + c9 * Fz;
+    }
+    // sixth order, Eq. (26)
+    k[K(2, 2, 2)] = (one - w[10]) * k[K(2, 2, 2)] + w[10] * pm * ninth;
+}
+
+}  // namespace lbfe

@@ -1,0 +1,87 @@
+// Internal declarations shared by the HIP kernels and the C-ABI host code of
+// the D3Q27 free-energy LB library.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "lbfe.h"
+
+namespace lbfe {
+
+constexpr int kBlock = 256;  // threads per workgroup (4 wave64s)
+
+// Kernel-side copy of the parameters, passed by value to every kernel.
+struct KP {
+    int nx, ny, nz;
+    unsigned plane;   // nx * ny
+    unsigned N;       // nx * ny * nz
+    int walls;        // solid planes z = 0 and z = nz-1
+    int z0, z1;       // fluid planes [z0, z1)
+    unsigned nfluid;  // (z1 - z0) * plane
+    double a, b, RT, kappa, nu;
+    double om[11];
+    int corr4, wet_mode;
+    double wet_value, lo, hi;  // wetting value and contact-line window
+    int xcd_remap;             // map consecutive tiles onto one XCD
+};
+
+// Device pointers of one context (all inside the caller's workspace).
+struct Bufs {
+    void *f[2];          // population lattices (current = f[cur])
+    double *rho;         // [N] density (solid planes: Eqs. (37)-(38))
+    void *j;             // [3][N] sum_i f_i c_i, compute precision
+    double *mu;          // [N] chemical potential (solid: Eq. (36))
+    void *F;             // [3][N] force, compute precision
+    void *phi;           // [3][N] (p_m - rho/3) u, compute precision, 0 at solid
+    int *flag;           // divergence / domain flag
+    double *part;        // reduction partials [nblk][8]
+    double *red;         // final reductions [8]
+    // adjoint
+    void *lam[2];        // adjoint populations
+    void *abuf;          // adjoint auxiliary fields (see adjoint kernels)
+    double *agrad;       // gradient partials
+};
+
+// Launchers (lbfe_kernels.hip).  All enqueue on `s` and return hipError_t.
+hipError_t launch_fill(hipStream_t s, void *p, size_t bytes);
+hipError_t launch_init(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, const double *rho0,
+                       const double *u0);
+hipError_t launch_aux(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur);
+hipError_t launch_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur);
+hipError_t launch_export(hipStream_t s, int prec, const KP &kp, const Bufs &b, int which, double *out);
+hipError_t launch_reduce(hipStream_t s, int prec, const KP &kp, const Bufs &b);
+hipError_t launch_get_pop(hipStream_t s, int prec, const KP &kp, const void *f, double *out);
+hipError_t launch_set_pop(hipStream_t s, int prec, const KP &kp, void *f, const double *in);
+hipError_t launch_check_rho0(hipStream_t s, const KP &kp, const double *rho0, int *flag);
+
+// adjoint (lbfe_adjoint.hip)
+size_t adjoint_aux_bytes(int prec, size_t N);
+size_t adjoint_grad_slots();
+hipError_t launch_adj_seed(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const double *dLdrho);
+hipError_t launch_adj_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const void *ft);
+hipError_t launch_adj_init(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const double *rho0,
+                           double *out);
+hipError_t launch_adj_grads(hipStream_t s, const KP &kp, const Bufs &b);
+
+inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+// Byte sizes per precision
+inline size_t real_bytes(int prec) { return prec == LBFE_FP64 ? 8 : 4; }
+inline size_t pop_bytes(int prec, size_t N) {
+    switch (prec) {
+        case LBFE_FP64: return 27 * 8 * N;
+        case LBFE_FP32: return 27 * 4 * N;
+        case LBFE_FP16_DEV: return 27 * 2 * N;
+        default: {  // 26 half planes, then one float plane (256-byte aligned)
+            size_t h = (26 * 2 * N + 255) & ~size_t(255);
+            return h + 4 * N;
+        }
+    }
+}
+inline size_t lambda_bytes(int prec, size_t N) { return 27 * real_bytes(prec) * N; }
+
+}  // namespace lbfe

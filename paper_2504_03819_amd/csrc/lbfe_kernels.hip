@@ -1,0 +1,479 @@
+// Forward kernels of the D3Q27 chemical-potential free-energy LB step
+// (arXiv:2504.03819, Sec. II B and Sec. III C) for gfx950.
+//
+// One time step t -> t+1 on the post-streaming state f(t) is five launches:
+//   k_moments   rho (double) and j = sum f c of every fluid node     Eq. (11)
+//   k_wall_rho  density of the solid nodes                      Eqs. (37)-(38)
+//   k_mu        mu = mu0(rho) - kappa lap_h rho                       Eq. (32)
+//   k_wall_mu   mu of the solid nodes                                 Eq. (36)
+//   k_force     F = (1/3 - rho) grad_h mu, u, phi = (p_m - rho/3) u   Eq. (12)
+//   k_collide   Q from phi, CM transform, collision, inverse, push-stream
+//               with halfway bounce-back              Eqs. (10), (21)-(28)
+// (the wall kernels only with solid planes).  Populations are SoA
+// [27][z][y][x]; one thread per node, x fastest, so every population load
+// and store of a wave64 is one contiguous 64-element run.
+#include <type_traits>
+
+#include "lbfe_device.h"
+
+namespace lbfe {
+namespace {
+
+template <int P> using real_t = typename Pol<P>::real;
+
+// --------------------------------------------------------------------------
+__global__ void k_fill(uint4 *p, size_t n16) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) p[i] = make_uint4(0, 0, 0, 0);
+}
+
+// --------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_moments(KP kp, const void *fq, double *rho, void *jq, int *flag) {
+    using real = real_t<P>;
+    const unsigned idx = tile_id(kp) * kBlock + threadIdx.x;
+    if (idx >= kp.nfluid) return;
+    const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
+    const Pops<P> f(fq, kp.N);
+    real v[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) v[i] = f.ld(i, n);
+    double r;
+    real jx, jy, jz;
+    moments(v, r, jx, jy, jz);
+    rho[n] = r;
+    real *j = (real *)jq;
+    j[n] = jx;
+    j[kp.N + n] = jy;
+    j[2 * (size_t)kp.N + n] = jz;
+    if (!(r > 0.0 && kp.b * r < 1.0)) *flag = 1;
+}
+
+// Weighted average over fluid neighbours of a solid node (Eqs. (36)/(37));
+// neighbours outside the box or on the solid planes have s_w = 0.
+__device__ inline double wall_average(const KP &kp, const double *g, int x, int y, int zs) {
+    const int xm = x == 0 ? kp.nx - 1 : x - 1, xp = x == kp.nx - 1 ? 0 : x + 1;
+    const int ym = y == 0 ? kp.ny - 1 : y - 1, yp = y == kp.ny - 1 ? 0 : y + 1;
+    const int X[3] = {xm, x, xp}, Y[3] = {ym, y, yp};
+    double num = 0.0, den = 0.0;
+#pragma unroll
+    for (int cz = -1; cz <= 1; ++cz) {
+        const int zz = zs + cz;
+        if (zz < 1 || zz > kp.nz - 2) continue;
+#pragma unroll
+        for (int cy = -1; cy <= 1; ++cy)
+#pragma unroll
+            for (int cx = -1; cx <= 1; ++cx) {
+                const double w = wq(cx, cy, cz);
+                num += w * g[(size_t)zz * kp.plane + (unsigned)Y[cy + 1] * kp.nx + X[cx + 1]];
+                den += w;
+            }
+    }
+    return num / den;
+}
+
+__global__ __launch_bounds__(kBlock) void k_wall_rho(KP kp, double *rho) {
+    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= 2 * kp.plane) return;
+    const int side = idx >= kp.plane;
+    const unsigned p = idx - (side ? kp.plane : 0u);
+    const int y = (int)(p / (unsigned)kp.nx), x = (int)(p - (unsigned)y * kp.nx);
+    const int zs = side ? kp.nz - 1 : 0;
+    const double rave = wall_average(kp, rho, x, y, zs);
+    double out = rave;
+    if (rave >= kp.lo && rave <= kp.hi) {  // contact-line window
+        if (kp.wet_mode == LBFE_WET_PHI)
+            out = fmin(fmax(kp.wet_value * rave, kp.lo), kp.hi);
+        else if (kp.wet_mode == LBFE_WET_DELTA)
+            out = fmin(fmax(rave - kp.wet_value, kp.lo), kp.hi);
+    }
+    rho[(size_t)zs * kp.plane + p] = out;
+}
+
+__global__ __launch_bounds__(kBlock) void k_wall_mu(KP kp, double *mu) {
+    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= 2 * kp.plane) return;
+    const int side = idx >= kp.plane;
+    const unsigned p = idx - (side ? kp.plane : 0u);
+    const int y = (int)(p / (unsigned)kp.nx), x = (int)(p - (unsigned)y * kp.nx);
+    const int zs = side ? kp.nz - 1 : 0;
+    mu[(size_t)zs * kp.plane + p] = wall_average(kp, mu, x, y, zs);
+}
+
+// mu = mu0(rho) - kappa lap_h rho, lap_h g = 6 sum_i w_i (g(x+c_i) - g(x)).
+__global__ __launch_bounds__(kBlock) void k_mu(KP kp, const double *rho, double *mu) {
+    const unsigned idx = tile_id(kp) * kBlock + threadIdx.x;
+    if (idx >= kp.nfluid) return;
+    const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
+    int x, y, z;
+    decompose(kp, n, x, y, z);
+    const Nb nb(kp, x, y, z);
+    const double r0 = rho[n];
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        if (i == kRest) continue;
+        s += wi(i) * (rho[nb.at(cxi(i), cyi(i), czi(i))] - r0);
+    }
+    mu[n] = mu_bulk(kp, r0) - kp.kappa * 6.0 * s;
+}
+
+// grad_h mu (double), F = (1/3 - rho) grad mu, u = (j + F/2)/rho,
+// phi = (p_m - rho/3) u.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_force(KP kp, const double *rho, const void *jq, const double *mu, void *Fq,
+                                                  void *phiq) {
+    using real = real_t<P>;
+    const unsigned idx = tile_id(kp) * kBlock + threadIdx.x;
+    if (idx >= kp.nfluid) return;
+    const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
+    int x, y, z;
+    decompose(kp, n, x, y, z);
+    const Nb nb(kp, x, y, z);
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        if (i == kRest) continue;
+        const double m = wi(i) * mu[nb.at(cxi(i), cyi(i), czi(i))];
+        if (cxi(i)) gx += cxi(i) * m;
+        if (cyi(i)) gy += cyi(i) * m;
+        if (czi(i)) gz += czi(i) * m;
+    }
+    const double r = rho[n];
+    const double c1 = 1.0 / 3.0 - r;
+    const real Fx = (real)(c1 * 3.0 * gx), Fy = (real)(c1 * 3.0 * gy), Fz = (real)(c1 * 3.0 * gz);
+    real *F = (real *)Fq;
+    F[n] = Fx;
+    F[kp.N + n] = Fy;
+    F[2 * (size_t)kp.N + n] = Fz;
+    const real *j = (const real *)jq;
+    const real rr = (real)r;
+    const real ux = (j[n] + (real)0.5 * Fx) / rr;
+    const real uy = (j[kp.N + n] + (real)0.5 * Fy) / rr;
+    const real uz = (j[2 * (size_t)kp.N + n] + (real)0.5 * Fz) / rr;
+    const double pm = (1.0 + mu[n]) / 3.0;
+    const real c2 = (real)(pm - r / 3.0);
+    real *phi = (real *)phiq;
+    phi[n] = c2 * ux;
+    phi[kp.N + n] = c2 * uy;
+    phi[2 * (size_t)kp.N + n] = c2 * uz;
+}
+
+// Fused collide + stream of one fluid node (push: f*_i(x) -> x + c_i, or
+// -> slot opp(i) of x when x + c_i is solid: halfway bounce-back).
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_collide(KP kp, const void *fin_q, void *fout_q, const double *mu,
+                                                    const void *Fq, const void *phiq) {
+    using real = real_t<P>;
+    const unsigned idx = tile_id(kp) * kBlock + threadIdx.x;
+    if (idx >= kp.nfluid) return;
+    const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
+    int x, y, z;
+    decompose(kp, n, x, y, z);
+    const Nb nb(kp, x, y, z);
+    const Pops<P> fin(fin_q, kp.N);
+    const Pops<P> fout(fout_q, kp.N);
+
+    real f[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) f[i] = fin.ld(i, n);
+    double rd;
+    real jx, jy, jz;
+    moments(f, rd, jx, jy, jz);
+    const real *F = (const real *)Fq;
+    const real Fx = F[n], Fy = F[kp.N + n], Fz = F[2 * (size_t)kp.N + n];
+    const real rho = (real)rd;
+    const real ux = (jx + (real)0.5 * Fx) / rho;
+    const real uy = (jy + (real)0.5 * Fy) / rho;
+    const real uz = (jz + (real)0.5 * Fz) / rho;
+    const real pm = (real)((1.0 + mu[n]) / 3.0);
+    real q200, q020, q002;
+    q_terms(kp, nb, (const real *)phiq, q200, q020, q002);
+    real q220 = 0, q202 = 0, q022 = 0;
+    if (kp.corr4) {  // Eq. (28)
+        const real third = (real)(1.0 / 3.0);
+        q220 = (q200 + q020) * third;
+        q202 = (q200 + q002) * third;
+        q022 = (q020 + q002) * third;
+    }
+    Rates<real> R;
+#pragma unroll
+    for (int k = 0; k < 11; ++k) R.w[k] = (real)kp.om[k];
+    R.w[1] = (real)1 / (rho * (real)kp.nu / pm + (real)0.5);
+
+    cm_forward(f, ux, uy, uz);
+    collide(f, R, Fx, Fy, Fz, pm, q200, q020, q002, q220, q202, q022);
+    cm_inverse(f, ux, uy, uz);
+
+    const bool wall_lo = kp.walls && z == 1;
+    const bool wall_hi = kp.walls && z == kp.nz - 2;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int cz = czi(i);
+        if ((cz < 0 && wall_lo) || (cz > 0 && wall_hi))
+            fout.st(26 - i, n, f[i]);
+        else
+            fout.st(i, nb.at(cxi(i), cyi(i), cz), f[i]);
+    }
+}
+
+// Initial populations: inverse CM transform of the Eq. (20) equilibrium.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_init(KP kp, const double *rho0, const double *u0, const double *mu,
+                                                 void *fq) {
+    using real = real_t<P>;
+    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= kp.nfluid) return;
+    const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
+    real k[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) k[i] = 0;
+    const real pm = (real)((1.0 + mu[n]) / 3.0);
+    k[K(0, 0, 0)] = (real)rho0[n];
+    k[K(2, 0, 0)] = k[K(0, 2, 0)] = k[K(0, 0, 2)] = pm;
+    k[K(2, 2, 0)] = k[K(2, 0, 2)] = k[K(0, 2, 2)] = pm * (real)(1.0 / 3.0);
+    k[K(2, 2, 2)] = pm * (real)(1.0 / 9.0);
+    real ux = 0, uy = 0, uz = 0;
+    if (u0) {
+        ux = (real)u0[n];
+        uy = (real)u0[kp.N + n];
+        uz = (real)u0[2 * (size_t)kp.N + n];
+    }
+    cm_inverse(k, ux, uy, uz);
+    const Pops<P> f(fq, kp.N);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) f.st(i, n, k[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_copy_fluid(KP kp, const double *src, double *dst) {
+    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= kp.nfluid) return;
+    const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
+    dst[n] = src[n];
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_rho(KP kp, const double *rho, int *flag) {
+    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= kp.nfluid) return;
+    const double r = rho[(unsigned)kp.z0 * kp.plane + idx];
+    if (!(r > 0.0 && kp.b * r < 1.0)) *flag = 1;
+}
+
+// Field export of the current state (aux arrays already evaluated).
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_export(KP kp, int which, const double *rho, const void *jq,
+                                                   const double *mu, const void *Fq, const void *phiq,
+                                                   double *out) {
+    using real = real_t<P>;
+    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= kp.N) return;
+    int x, y, z;
+    decompose(kp, n, x, y, z);
+    const bool fluid = z >= kp.z0 && z < kp.z1;
+    const size_t N = kp.N;
+    const real *F = (const real *)Fq;
+    switch (which) {
+        case LBFE_FIELD_RHO: out[n] = rho[n]; break;
+        case LBFE_FIELD_MU: out[n] = mu[n]; break;
+        case LBFE_FIELD_PM: out[n] = (1.0 + mu[n]) / 3.0; break;
+        case LBFE_FIELD_F:
+            for (int a = 0; a < 3; ++a) out[a * N + n] = fluid ? (double)F[a * N + n] : 0.0;
+            break;
+        case LBFE_FIELD_U: {
+            const real *j = (const real *)jq;
+            const real rr = (real)rho[n];
+            for (int a = 0; a < 3; ++a)
+                out[a * N + n] = fluid ? (double)((j[a * N + n] + (real)0.5 * F[a * N + n]) / rr) : 0.0;
+            break;
+        }
+        case LBFE_FIELD_Q: {
+            real q[3] = {0, 0, 0};
+            if (fluid) {
+                const Nb nb(kp, x, y, z);
+                q_terms(kp, nb, (const real *)phiq, q[0], q[1], q[2]);
+            }
+            for (int a = 0; a < 3; ++a) out[a * N + n] = (double)q[a];
+            break;
+        }
+        default: break;
+    }
+}
+
+// Deterministic reductions: fixed per-block tree, then one block over the
+// block partials in a fixed order.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_reduce_part(KP kp, const double *rho, const void *jq, const void *Fq,
+                                                        double *part) {
+    using real = real_t<P>;
+    __shared__ double s[8][kBlock];
+    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (idx < kp.nfluid) {
+        const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
+        const size_t N = kp.N;
+        const real *j = (const real *)jq, *F = (const real *)Fq;
+        const double r = rho[n];
+        v[0] = r;
+        double u2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            v[1 + a] = (double)j[a * N + n];
+            v[4 + a] = (double)F[a * N + n];
+            const double u = ((double)j[a * N + n] + 0.5 * (double)F[a * N + n]) / r;
+            u2 += u * u;
+        }
+        v[7] = sqrt(u2);
+    }
+    for (int k = 0; k < 8; ++k) s[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            for (int k = 0; k < 7; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + h];
+            s[7][threadIdx.x] = fmax(s[7][threadIdx.x], s[7][threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) part[(size_t)blockIdx.x * 8 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_final(unsigned nblk, const double *part, double *out) {
+    __shared__ double s[8][kBlock];
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (unsigned b = threadIdx.x; b < nblk; b += kBlock) {
+        for (int k = 0; k < 7; ++k) v[k] += part[(size_t)b * 8 + k];
+        v[7] = fmax(v[7], part[(size_t)b * 8 + 7]);
+    }
+    for (int k = 0; k < 8; ++k) s[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) {
+            for (int k = 0; k < 7; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + h];
+            s[7][threadIdx.x] = fmax(s[7][threadIdx.x], s[7][threadIdx.x + h]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_get_pop(KP kp, const void *fq, double *out) {
+    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= kp.N) return;
+    const unsigned z = n / kp.plane;
+    const bool fluid = (int)z >= kp.z0 && (int)z < kp.z1;
+    const Pops<P> f(fq, kp.N);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) out[(size_t)i * kp.N + n] = fluid ? (double)f.ld(i, n) : 0.0;
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_set_pop(KP kp, void *fq, const double *in) {
+    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= kp.nfluid) return;
+    const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
+    const Pops<P> f(fq, kp.N);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) f.st(i, n, (real_t<P>)in[(size_t)i * kp.N + n]);
+}
+
+// --------------------------------------------------------------------------
+template <int P> hipError_t aux_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur) {
+    const unsigned gf = nblocks(kp.nfluid), gw = nblocks(2 * (size_t)kp.plane);
+    k_moments<P><<<gf, kBlock, 0, s>>>(kp, b.f[cur], b.rho, b.j, b.flag);
+    if (kp.walls) k_wall_rho<<<gw, kBlock, 0, s>>>(kp, b.rho);
+    k_mu<<<gf, kBlock, 0, s>>>(kp, b.rho, b.mu);
+    if (kp.walls) k_wall_mu<<<gw, kBlock, 0, s>>>(kp, b.mu);
+    k_force<P><<<gf, kBlock, 0, s>>>(kp, b.rho, b.j, b.mu, b.F, b.phi);
+    return hipGetLastError();
+}
+
+template <int P> hipError_t step_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur) {
+    hipError_t e = aux_impl<P>(s, kp, b, cur);
+    if (e != hipSuccess) return e;
+    k_collide<P><<<nblocks(kp.nfluid), kBlock, 0, s>>>(kp, b.f[cur], b.f[1 - cur], b.mu, b.F, b.phi);
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t init_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur, const double *rho0, const double *u0) {
+    const unsigned gf = nblocks(kp.nfluid), gw = nblocks(2 * (size_t)kp.plane);
+    k_copy_fluid<<<gf, kBlock, 0, s>>>(kp, rho0, b.rho);
+    if (kp.walls) k_wall_rho<<<gw, kBlock, 0, s>>>(kp, b.rho);
+    k_mu<<<gf, kBlock, 0, s>>>(kp, b.rho, b.mu);
+    k_init<P><<<gf, kBlock, 0, s>>>(kp, b.rho, u0, b.mu, b.f[cur]);
+    return hipGetLastError();
+}
+
+// Run f(std::integral_constant<int, P>) for the storage form P = prec.
+template <class Fn> hipError_t dispatch(int prec, Fn &&fn) {
+    switch (prec) {
+        case LBFE_FP64: return fn(std::integral_constant<int, LBFE_FP64>{});
+        case LBFE_FP32: return fn(std::integral_constant<int, LBFE_FP32>{});
+        case LBFE_FP16_DEV: return fn(std::integral_constant<int, LBFE_FP16_DEV>{});
+        default: return fn(std::integral_constant<int, LBFE_FP16_DEV_F0FP32>{});
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fill(hipStream_t s, void *p, size_t bytes) {
+    const size_t n16 = bytes / 16;
+    if (!n16) return hipSuccess;
+    unsigned g = (unsigned)((n16 + kBlock - 1) / kBlock);
+    if (g > 65536) g = 65536;
+    k_fill<<<g, kBlock, 0, s>>>((uint4 *)p, n16);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, const double *rho0,
+                       const double *u0) {
+    return dispatch(prec, [&](auto pc) { return init_impl<decltype(pc)::value>(s, kp, b, cur, rho0, u0); });
+}
+
+hipError_t launch_aux(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur) {
+    return dispatch(prec, [&](auto pc) { return aux_impl<decltype(pc)::value>(s, kp, b, cur); });
+}
+
+hipError_t launch_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur) {
+    return dispatch(prec, [&](auto pc) { return step_impl<decltype(pc)::value>(s, kp, b, cur); });
+}
+
+hipError_t launch_export(hipStream_t s, int prec, const KP &kp, const Bufs &b, int which, double *out) {
+    return dispatch(prec, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        k_export<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, which, b.rho, b.j, b.mu, b.F, b.phi, out);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_reduce(hipStream_t s, int prec, const KP &kp, const Bufs &b) {
+    const unsigned g = nblocks(kp.nfluid);
+    return dispatch(prec, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        k_reduce_part<P><<<g, kBlock, 0, s>>>(kp, b.rho, b.j, b.F, b.part);
+        k_reduce_final<<<1, kBlock, 0, s>>>(g, b.part, b.red);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_get_pop(hipStream_t s, int prec, const KP &kp, const void *f, double *out) {
+    return dispatch(prec, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        k_get_pop<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, f, out);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_set_pop(hipStream_t s, int prec, const KP &kp, void *f, const double *in) {
+    return dispatch(prec, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        k_set_pop<P><<<nblocks(kp.nfluid), kBlock, 0, s>>>(kp, f, in);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_check_rho0(hipStream_t s, const KP &kp, const double *rho0, int *flag) {
+    k_check_rho<<<nblocks(kp.nfluid), kBlock, 0, s>>>(kp, rho0, flag);
+    return hipGetLastError();
+}
+
+}  // namespace lbfe

@@ -1,0 +1,215 @@
+"""Parity of the HIP FP64 path with the CPU oracle: per-step fields and
+populations from identical states (max relative error 1e-11 per field, per
+population), short trajectories, and sampled nodes at the 128^3 benchmark
+size in the launch configuration the benchmark times."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import (DT, droplet_rho, gpu_fields, make_sim, oracle_fields, oracle_params, rel_err, say)
+from oracle import eos, lbm
+from paper_2504_03819_amd import inputs, lbfe
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-11
+
+
+def check_state(sim, f_state, label):
+    """Fields of f(t) and populations of f(t+1), GPU vs oracle."""
+    p = oracle_params(sim)
+    sim.set_populations(f_state)
+    g = gpu_fields(sim)
+    o = oracle_fields(f_state, p)
+    errs = {k: rel_err(g[k], o[k]) for k in o}
+    sim.step(1)
+    fg = sim.populations().cpu()
+    fo = lbm.step(f_state, p)
+    sl = slice(1, -1) if p.walls_z else slice(None)
+    errs["f"] = max(rel_err(fg[i, sl], fo[i, sl]) for i in range(27))
+    say(f"{label}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v < TOL, (label, k, v)
+
+
+CASES = [
+    # (label, shape (nz, ny, nx), walls, extra params)
+    ("periodic 8^3", (8, 8, 8), False, {}),
+    ("ragged 10x12x17", (10, 12, 17), False, {}),
+    ("flat 128x4x4", (128, 4, 4), False, {}),
+    ("rates random, no corr4", (9, 11, 13), False,
+     dict(omega=[0.7, 1.0, 1.3, 0.6, 1.8, 1.1, 0.5, 1.9, 0.9, 1.4, 1.2], corr4=0)),
+    ("walls neutral", (12, 9, 7), True, dict(wet_mode=0)),
+    ("walls phi 1.6", (12, 9, 7), True, dict(wet_mode=1, wet_value=1.6)),
+    ("walls drho 1.8", (12, 9, 7), True, dict(wet_mode=2, wet_value=1.8)),
+]
+
+
+@pytest.mark.parametrize("label,shape,walls,extra", CASES, ids=[c[0] for c in CASES])
+def test_one_step_parity(label, shape, walls, extra):
+    say(f"case {label}")
+    T = eos.temperature(0.7 if walls else 0.85)
+    nz, ny, nx = shape
+    sim = make_sim(nx=nx, ny=ny, nz=nz, T=T, walls_z=int(walls), **extra)
+    p = oracle_params(sim)
+    rho0 = droplet_rho(shape, T, walls=walls)
+    g = np.random.Generator(np.random.PCG64(17))
+    u0 = 0.03 * (g.uniform(-1, 1, (3,) + shape))
+    f0 = lbm.init(torch.tensor(rho0), p, torch.tensor(u0))
+    # GPU initialiser parity
+    sim.init_density(torch.tensor(rho0), torch.tensor(u0))
+    e_init = rel_err(sim.populations().cpu(), f0)
+    say(f"{label}: init f err={e_init:.2e}")
+    assert e_init < TOL
+    # leave the equilibrium manifold so every moment order is exercised
+    f = f0 + torch.tensor(inputs.uniform_noise(tuple(f0.shape), 2e-4, 23)) * (f0 != 0)
+    check_state(sim, f, label)
+
+
+def test_trajectory_stationary_droplet_32():
+    """The 32^3 droplet at 0.9 Tc (radius 8, noise 1e-6): 60 steps, fields and
+    populations against the oracle; the full 500 steps run in the slow test."""
+    T = eos.temperature(0.9)
+    sim = make_sim(nx=32, ny=32, nz=32, T=T)
+    p = oracle_params(sim)
+    rho0, _ = inputs.stationary_droplet(sim.rho_l, sim.rho_v)
+    sim.init_density(torch.tensor(rho0))
+    f = lbm.init(torch.tensor(rho0), p)
+    steps = 60
+    sim.step(steps)
+    f = lbm.run(f, p, steps)
+    g = gpu_fields(sim)
+    o = oracle_fields(f, p)
+    errs = {k: rel_err(g[k], o[k]) for k in o}
+    errs["f"] = rel_err(sim.populations().cpu(), f)
+    say("droplet32 t=60: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v < TOL, (k, v)
+
+
+def test_trajectory_sessile_droplet_walls():
+    T = eos.temperature(0.7)
+    shape = (14, 12, 16)
+    sim = make_sim(nx=16, ny=12, nz=14, T=T, walls_z=1, wet_mode=lbfe.WET_PHI, wet_value=1.3)
+    p = oracle_params(sim)
+    rho0 = droplet_rho(shape, T, radius=5.0, walls=True, noise=0)
+    sim.init_density(torch.tensor(rho0))
+    f = lbm.init(torch.tensor(rho0), p)
+    sim.step(30)
+    f = lbm.run(f, p, 30)
+    fg = sim.populations().cpu()
+    e = rel_err(fg[:, 1:-1], f[:, 1:-1])
+    g = gpu_fields(sim)
+    o = oracle_fields(f, p)
+    errs = {k: rel_err(g[k], o[k]) for k in o}
+    say(f"sessile t=30: f={e:.2e} " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    assert e < TOL and all(v < TOL for v in errs.values())
+
+
+def _window_step(f_win, p_win):
+    return lbm.step(f_win, p_win)
+
+
+def test_full_size_moving_droplet_sampled():
+    """128^3 moving droplet (the benchmark workload), one step in the
+    benchmark's launch configuration; the oracle recomputes sampled nodes
+    from 13^3 windows of f(t) (a node's update depends on f(t) within 4
+    nodes: 3 stencil hops plus streaming), interior 5^3 compared."""
+    n = 128
+    T = eos.temperature(0.85)
+    sim = make_sim(nx=n, ny=n, nz=n, T=T)
+    rho0, u0 = inputs.moving_droplet(sim.rho_l, sim.rho_v)
+    sim.init_density(torch.tensor(rho0), torch.tensor(u0))
+    sim.step(20)
+    f_t = sim.populations().cpu()
+    sim.step(1)
+    f_t1 = sim.populations().cpu()
+    p = oracle_params(sim)
+    g = np.random.Generator(np.random.PCG64(5))
+    # sample centres on the interface, in the liquid and in the vapour
+    centres = [tuple(int(v) for v in g.integers(0, n, 3)) for _ in range(4)]
+    centres += [(64, 64, 64 + 24), (64, 64 + 24, 64), (0, 0, 0), (127, 64, 40)]
+    worst = 0.0
+    for (cz, cy, cx) in centres:
+        idx = [np.arange(c - 6, c + 7) % n for c in (cz, cy, cx)]
+        win = f_t[:, idx[0]][:, :, idx[1]][:, :, :, idx[2]]
+        pw = lbm.Params(13, 13, 13, T=p.T, kappa=p.kappa, nu=p.nu, omega=p.omega, corr4=p.corr4,
+                        rho_l=p.rho_l, rho_v=p.rho_v)
+        fo = _window_step(win, pw)[:, 4:9, 4:9, 4:9]
+        fg = f_t1[:, idx[0][4:9]][:, :, idx[1][4:9]][:, :, :, idx[2][4:9]]
+        e = float((fg - fo).abs().max() / fo.abs().max())
+        worst = max(worst, e)
+    say(f"128^3 sampled windows: max rel err {worst:.2e}")
+    assert worst < TOL
+
+
+def test_step_is_deterministic():
+    T = eos.temperature(0.8)
+    sim = make_sim(nx=24, ny=20, nz=16, T=T)
+    rho0 = droplet_rho((16, 20, 24), T, noise=1e-2, seed=4)
+    out = []
+    for _ in range(2):
+        sim.init_density(torch.tensor(rho0))
+        sim.step(10)
+        out.append(sim.get_state().clone())
+    assert torch.equal(out[0], out[1])
+
+
+def test_reductions_and_invariants():
+    T = eos.temperature(0.85)
+    n = 20
+    sim = make_sim(nx=n, ny=n, nz=n, T=T)
+    rho0 = droplet_rho((n, n, n), T, noise=1e-2)
+    g = np.random.Generator(np.random.PCG64(8))
+    u0 = 0.02 * g.uniform(-1, 1, (3, n, n, n))
+    sim.init_density(torch.tensor(rho0), torch.tensor(u0))
+    r0 = sim.reduce()
+    assert abs(r0[0] - rho0.sum()) < 1e-12 * rho0.sum()
+    for _ in range(5):
+        r = sim.reduce()
+        sim.step(1)
+        r1 = sim.reduce()
+        assert abs(r1[0] - r0[0]) < 1e-13 * r0[0]
+        for a in range(3):  # momentum balance: sum j(t+1) - sum j(t) = sum F(t)
+            assert abs((r1[1 + a] - r[1 + a]) - r[4 + a]) < 1e-12
+    fl = sim.fields()
+    assert abs(float(fl["u"].norm(dim=0).max()) - r1[7]) < 1e-14
+
+
+def test_invalid_density_and_divergence_flag():
+    T = eos.temperature(0.85)
+    sim = make_sim(nx=8, ny=8, nz=8, T=T, check_every=1)
+    rho0 = torch.full((8, 8, 8), 2.0, dtype=DT)
+    rho0[3, 3, 3] = float("nan")
+    with pytest.raises(lbfe.LBFEError) as ei:
+        sim.init_density(rho0)
+    assert ei.value.code == lbfe.E_INVAL
+    rho0[3, 3, 3] = 11.0   # beyond 1/b = 10.5
+    with pytest.raises(lbfe.LBFEError):
+        sim.init_density(rho0)
+    with pytest.raises(lbfe.LBFEError) as ei:
+        sim.step(1)        # no state yet
+    assert ei.value.code == lbfe.E_STATE
+    rho0[3, 3, 3] = 2.0
+    sim.init_density(rho0)
+    f = sim.populations()
+    f[13, 2, 2, 2] += 12.0  # push one node outside the EOS domain
+    sim.set_populations(f)
+    with pytest.raises(lbfe.LBFEError) as ei:
+        sim.step(2)
+    assert ei.value.code == lbfe.E_DIVERGED
+
+
+def test_state_roundtrip_and_counter():
+    T = eos.temperature(0.85)
+    sim = make_sim(nx=12, ny=12, nz=12, T=T)
+    rho0 = droplet_rho((12, 12, 12), T)
+    sim.init_density(torch.tensor(rho0))
+    sim.step(3)
+    s3 = sim.get_state().clone()
+    sim.step(4)
+    s7 = sim.get_state().clone()
+    assert sim.step_count == 7
+    sim.set_state(s3, 3)
+    sim.step(4)
+    assert sim.step_count == 7
+    assert torch.equal(sim.get_state(), s7)
