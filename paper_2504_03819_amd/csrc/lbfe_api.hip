@@ -346,6 +346,42 @@ int lbfe_step(lbfe_ctx *c, int64_t nsteps) {
     return LBFE_OK;
 }
 
+int lbfe_step_timed(lbfe_ctx *c, int64_t nsteps, double kernel_ms[6]) {
+    int r = need_init(c);
+    if (r) return r;
+    if (nsteps < 0 || !kernel_ms) return fail(c, LBFE_E_INVAL, "nsteps < 0 or null kernel_ms");
+    hipEvent_t ev[7];
+    for (int k = 0; k < 7; ++k)
+        if (hipEventCreate(&ev[k]) != hipSuccess) {
+            for (int q = 0; q < k; ++q) (void)hipEventDestroy(ev[q]);
+            return fail(c, LBFE_E_DEVICE, "hipEventCreate failed");
+        }
+    for (int k = 0; k < 6; ++k) kernel_ms[k] = 0.0;
+    int rc = LBFE_OK;
+    for (int64_t s = 0; s < nsteps && rc == LBFE_OK; ++s) {
+        hipError_t e = launch_step_timed(c->stream, c->p.precision, c->kp, c->b, c->cur, ev);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[6]);
+        if (e != hipSuccess) {
+            rc = hip_fail(c, e, "step_timed");
+            break;
+        }
+        for (int k = 0; k < 6; ++k) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+            kernel_ms[k] += ms;
+        }
+        c->cur ^= 1;
+        c->step++;
+    }
+    for (int k = 0; k < 7; ++k) (void)hipEventDestroy(ev[k]);
+    if (rc == LBFE_OK) {
+        int flag = 0;
+        if ((rc = read_flag(c, flag))) return rc;
+        if (flag) return fail(c, LBFE_E_DIVERGED, "diverged during timed steps");
+    }
+    return rc;
+}
+
 int lbfe_step_count(const lbfe_ctx *c, int64_t *step) {
     if (!c || !step) return LBFE_E_INVAL;
     *step = c->step;

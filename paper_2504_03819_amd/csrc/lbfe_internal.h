@@ -52,6 +52,7 @@ hipError_t launch_init(hipStream_t s, int prec, const KP &kp, const Bufs &b, int
                        const double *u0);
 hipError_t launch_aux(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur);
 hipError_t launch_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur);
+hipError_t launch_step_timed(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, hipEvent_t *ev7);
 hipError_t launch_export(hipStream_t s, int prec, const KP &kp, const Bufs &b, int which, double *out);
 hipError_t launch_reduce(hipStream_t s, int prec, const KP &kp, const Bufs &b);
 hipError_t launch_get_pop(hipStream_t s, int prec, const KP &kp, const void *f, double *out);

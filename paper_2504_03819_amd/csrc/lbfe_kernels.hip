@@ -376,20 +376,35 @@ __global__ __launch_bounds__(kBlock) void k_set_pop(KP kp, void *fq, const doubl
 }
 
 // --------------------------------------------------------------------------
-template <int P> hipError_t aux_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur) {
+// One step's launches.  With `ev` non-null, HIP events are recorded on the
+// stream before the first kernel and after each of the six kernel classes
+// (moments, wall density, mu, wall mu, force, collide-stream).
+template <int P>
+hipError_t aux_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur, hipEvent_t *ev = nullptr) {
     const unsigned gf = nblocks(kp.nfluid), gw = nblocks(2 * (size_t)kp.plane);
+    auto mark = [&](int k) {
+        if (ev) (void)hipEventRecord(ev[k], s);
+    };
+    mark(0);
     k_moments<P><<<gf, kBlock, 0, s>>>(kp, b.f[cur], b.rho, b.j, b.flag);
+    mark(1);
     if (kp.walls) k_wall_rho<<<gw, kBlock, 0, s>>>(kp, b.rho);
+    mark(2);
     k_mu<<<gf, kBlock, 0, s>>>(kp, b.rho, b.mu);
+    mark(3);
     if (kp.walls) k_wall_mu<<<gw, kBlock, 0, s>>>(kp, b.mu);
+    mark(4);
     k_force<P><<<gf, kBlock, 0, s>>>(kp, b.rho, b.j, b.mu, b.F, b.phi);
+    mark(5);
     return hipGetLastError();
 }
 
-template <int P> hipError_t step_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur) {
-    hipError_t e = aux_impl<P>(s, kp, b, cur);
+template <int P>
+hipError_t step_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur, hipEvent_t *ev = nullptr) {
+    hipError_t e = aux_impl<P>(s, kp, b, cur, ev);
     if (e != hipSuccess) return e;
     k_collide<P><<<nblocks(kp.nfluid), kBlock, 0, s>>>(kp, b.f[cur], b.f[1 - cur], b.mu, b.F, b.phi);
+    if (ev) (void)hipEventRecord(ev[6], s);
     return hipGetLastError();
 }
 
@@ -435,6 +450,10 @@ hipError_t launch_aux(hipStream_t s, int prec, const KP &kp, const Bufs &b, int 
 
 hipError_t launch_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur) {
     return dispatch(prec, [&](auto pc) { return step_impl<decltype(pc)::value>(s, kp, b, cur); });
+}
+
+hipError_t launch_step_timed(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, hipEvent_t *ev) {
+    return dispatch(prec, [&](auto pc) { return step_impl<decltype(pc)::value>(s, kp, b, cur, ev); });
 }
 
 hipError_t launch_export(hipStream_t s, int prec, const KP &kp, const Bufs &b, int which, double *out) {

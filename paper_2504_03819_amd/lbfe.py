@@ -61,6 +61,7 @@ def lib():
         "lbfe_init_density": (c_int, [V, V, V]),
         "lbfe_step": (c_int, [V, c_int64]),
         "lbfe_step_count": (c_int, [V, POINTER(c_int64)]),
+        "lbfe_step_timed": (c_int, [V, c_int64, POINTER(c_double)]),
         "lbfe_fields": (c_int, [V, V, V, V, V]),
         "lbfe_field": (c_int, [V, c_int, V]),
         "lbfe_state_bytes": (c_int, [V, POINTER(c_size_t)]),
@@ -182,6 +183,15 @@ class Simulation:
 
     def step(self, n=1):
         self._check(lib().lbfe_step(self._ctx, c_int64(int(n))))
+
+    KERNELS = ("moments", "wall_rho", "mu", "wall_mu", "force", "collide_stream")
+
+    def step_timed(self, n):
+        """Run n steps with HIP events around each kernel; returns the summed
+        milliseconds per kernel class."""
+        out = (c_double * 6)()
+        self._check(lib().lbfe_step_timed(self._ctx, c_int64(int(n)), out))
+        return dict(zip(self.KERNELS, list(out)))
 
     @property
     def step_count(self):
