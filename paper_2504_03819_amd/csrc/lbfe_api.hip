@@ -4,6 +4,7 @@
 // lbfe_adjoint.hip.
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -258,7 +259,10 @@ int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out) {
     k.wet_value = q.wet_value;
     k.lo = 0.05 * q.rho_l + 0.95 * q.rho_v;
     k.hi = 0.95 * q.rho_l + 0.05 * q.rho_v;
-    k.xcd_remap = 1;
+    // Tile-to-XCD remapping: measured neutral to slightly slower for these
+    // streaming kernels, so off by default (LBFE_XCD_REMAP=1 enables it).
+    const char *remap = std::getenv("LBFE_XCD_REMAP");
+    k.xcd_remap = (remap && remap[0] == '1') ? 1 : 0;
     *out = c;
     return LBFE_OK;
 }

@@ -31,20 +31,27 @@ template <> struct Pol<LBFE_FP64> { using real = double; };
 
 template <int P> struct Pops;
 
+// Population storage is row-blocked: for every x-row (z, y) the 27
+// populations are stored one after another, each as nx contiguous values,
+// i.e. element (i, z, y, x) sits at ((z ny + y) 27 + i) nx + x.  A wave of
+// 64 x-consecutive threads touches one contiguous run per population, and
+// the 27 runs of a row share DRAM pages.
 template <> struct Pops<LBFE_FP64> {
     double *p;
-    unsigned N;
-    __device__ Pops(const void *q, unsigned n) : p((double *)q), N(n) {}
-    __device__ double ld(int i, unsigned n) const { return p[(size_t)i * N + n]; }
-    __device__ void st(int i, unsigned n, double v) const { p[(size_t)i * N + n] = v; }
+    unsigned nx;
+    __device__ Pops(const void *q, const KP &kp) : p((double *)q), nx((unsigned)kp.nx) {}
+    __device__ size_t off(int i, unsigned row, unsigned x) const { return ((size_t)row * 27 + i) * nx + x; }
+    __device__ double ld(int i, unsigned row, unsigned x) const { return p[off(i, row, x)]; }
+    __device__ void st(int i, unsigned row, unsigned x, double v) const { p[off(i, row, x)] = v; }
 };
 
 template <> struct Pops<LBFE_FP32> {
     float *p;
-    unsigned N;
-    __device__ Pops(const void *q, unsigned n) : p((float *)q), N(n) {}
-    __device__ float ld(int i, unsigned n) const { return p[(size_t)i * N + n]; }
-    __device__ void st(int i, unsigned n, float v) const { p[(size_t)i * N + n] = v; }
+    unsigned nx;
+    __device__ Pops(const void *q, const KP &kp) : p((float *)q), nx((unsigned)kp.nx) {}
+    __device__ size_t off(int i, unsigned row, unsigned x) const { return ((size_t)row * 27 + i) * nx + x; }
+    __device__ float ld(int i, unsigned row, unsigned x) const { return p[off(i, row, x)]; }
+    __device__ void st(int i, unsigned row, unsigned x, float v) const { p[off(i, row, x)] = v; }
 };
 
 // Half-precision deviation from the rest-state weight, scaled by the weight:
@@ -62,28 +69,32 @@ __device__ inline __half enc16(int i, float f) {
 
 template <> struct Pops<LBFE_FP16_DEV> {
     __half *p;
-    unsigned N;
-    __device__ Pops(const void *q, unsigned n) : p((__half *)q), N(n) {}
-    __device__ float ld(int i, unsigned n) const { return dec16(i, p[(size_t)i * N + n]); }
-    __device__ void st(int i, unsigned n, float v) const { p[(size_t)i * N + n] = enc16(i, v); }
+    unsigned nx;
+    __device__ Pops(const void *q, const KP &kp) : p((__half *)q), nx((unsigned)kp.nx) {}
+    __device__ size_t off(int i, unsigned row, unsigned x) const { return ((size_t)row * 27 + i) * nx + x; }
+    __device__ float ld(int i, unsigned row, unsigned x) const { return dec16(i, p[off(i, row, x)]); }
+    __device__ void st(int i, unsigned row, unsigned x, float v) const { p[off(i, row, x)] = enc16(i, v); }
 };
 
-// Rest population in float, the 26 moving ones as half deviations.
+// Rest population in float ([z][y][x] plane after the half rows), the 26
+// moving ones as half deviations, row-blocked 26 per row.
 template <> struct Pops<LBFE_FP16_DEV_F0FP32> {
     __half *p;
     float *p0;
-    unsigned N;
-    __device__ Pops(const void *q, unsigned n)
-        : p((__half *)q), p0((float *)((char *)q + ((26 * 2 * (size_t)n + 255) & ~size_t(255)))), N(n) {}
+    unsigned nx;
+    __device__ Pops(const void *q, const KP &kp)
+        : p((__half *)q), p0((float *)((char *)q + ((26 * 2 * (size_t)kp.N + 255) & ~size_t(255)))),
+          nx((unsigned)kp.nx) {}
     __device__ static int slot(int i) { return i < kRest ? i : i - 1; }
-    __device__ float ld(int i, unsigned n) const {
-        return i == kRest ? p0[n] : dec16(i, p[(size_t)slot(i) * N + n]);
+    __device__ size_t off(int i, unsigned row, unsigned x) const { return ((size_t)row * 26 + slot(i)) * nx + x; }
+    __device__ float ld(int i, unsigned row, unsigned x) const {
+        return i == kRest ? p0[(size_t)row * nx + x] : dec16(i, p[off(i, row, x)]);
     }
-    __device__ void st(int i, unsigned n, float v) const {
+    __device__ void st(int i, unsigned row, unsigned x, float v) const {
         if (i == kRest)
-            p0[n] = v;
+            p0[(size_t)row * nx + x] = v;
         else
-            p[(size_t)slot(i) * N + n] = enc16(i, v);
+            p[off(i, row, x)] = enc16(i, v);
     }
 };
 
@@ -99,21 +110,28 @@ __device__ inline unsigned tile_id(const KP &kp) {
     return k * q + (k < r ? k : r) + (b >> 3);
 }
 
-// Neighbour offsets of node (x, y, z) with periodic wrap.
+// Neighbour offsets of node (x, y, z) with periodic wrap: X, Y, Z give node
+// indices (Y in units of nx, Z of nx ny); RY, RZ give x-row indices.
 struct Nb {
-    unsigned X[3], Y[3], Z[3];
+    unsigned X[3], Y[3], Z[3], RY[3], RZ[3];
     __device__ Nb(const KP &kp, int x, int y, int z) {
         X[0] = x == 0 ? kp.nx - 1 : x - 1;
         X[1] = x;
         X[2] = x == kp.nx - 1 ? 0 : x + 1;
-        Y[0] = (y == 0 ? kp.ny - 1 : y - 1) * (unsigned)kp.nx;
-        Y[1] = y * (unsigned)kp.nx;
-        Y[2] = (y == kp.ny - 1 ? 0 : y + 1) * (unsigned)kp.nx;
-        Z[0] = (z == 0 ? kp.nz - 1 : z - 1) * kp.plane;
-        Z[1] = z * kp.plane;
-        Z[2] = (z == kp.nz - 1 ? 0 : z + 1) * kp.plane;
+        RY[0] = y == 0 ? kp.ny - 1 : y - 1;
+        RY[1] = y;
+        RY[2] = y == kp.ny - 1 ? 0 : y + 1;
+        RZ[0] = (z == 0 ? kp.nz - 1 : z - 1) * (unsigned)kp.ny;
+        RZ[1] = z * (unsigned)kp.ny;
+        RZ[2] = (z == kp.nz - 1 ? 0 : z + 1) * (unsigned)kp.ny;
+        for (int k = 0; k < 3; ++k) {
+            Y[k] = RY[k] * (unsigned)kp.nx;
+            Z[k] = RZ[k] * (unsigned)kp.nx;
+        }
     }
     __device__ unsigned at(int cx, int cy, int cz) const { return X[cx + 1] + Y[cy + 1] + Z[cz + 1]; }
+    __device__ unsigned row(int cy, int cz) const { return RY[cy + 1] + RZ[cz + 1]; }
+    __device__ unsigned xo(int cx) const { return X[cx + 1]; }
 };
 
 __device__ inline void decompose(const KP &kp, unsigned n, int &x, int &y, int &z) {

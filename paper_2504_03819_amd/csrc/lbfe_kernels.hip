@@ -9,9 +9,10 @@
 //   k_force     F = (1/3 - rho) grad_h mu, u, phi = (p_m - rho/3) u   Eq. (12)
 //   k_collide   Q from phi, CM transform, collision, inverse, push-stream
 //               with halfway bounce-back              Eqs. (10), (21)-(28)
-// (the wall kernels only with solid planes).  Populations are SoA
-// [27][z][y][x]; one thread per node, x fastest, so every population load
-// and store of a wave64 is one contiguous 64-element run.
+// (the wall kernels only with solid planes).  Populations are row-blocked
+// (each x-row holds its 27 populations as 27 contiguous runs); one thread per
+// node, x fastest, so every population load and store of a wave64 is one
+// contiguous 64-element run.
 #include <type_traits>
 
 #include "lbfe_device.h"
@@ -34,10 +35,11 @@ __global__ __launch_bounds__(kBlock) void k_moments(KP kp, const void *fq, doubl
     const unsigned idx = tile_id(kp) * kBlock + threadIdx.x;
     if (idx >= kp.nfluid) return;
     const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
-    const Pops<P> f(fq, kp.N);
+    const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
+    const Pops<P> f(fq, kp);
     real v[27];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) v[i] = f.ld(i, n);
+    for (int i = 0; i < 27; ++i) v[i] = f.ld(i, row, x);
     double r;
     real jx, jy, jz;
     moments(v, r, jx, jy, jz);
@@ -171,12 +173,13 @@ __global__ __launch_bounds__(kBlock) void k_collide(KP kp, const void *fin_q, vo
     int x, y, z;
     decompose(kp, n, x, y, z);
     const Nb nb(kp, x, y, z);
-    const Pops<P> fin(fin_q, kp.N);
-    const Pops<P> fout(fout_q, kp.N);
+    const Pops<P> fin(fin_q, kp);
+    const Pops<P> fout(fout_q, kp);
+    const unsigned row = nb.row(0, 0);
 
     real f[27];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) f[i] = fin.ld(i, n);
+    for (int i = 0; i < 27; ++i) f[i] = fin.ld(i, row, (unsigned)x);
     double rd;
     real jx, jy, jz;
     moments(f, rd, jx, jy, jz);
@@ -211,9 +214,9 @@ __global__ __launch_bounds__(kBlock) void k_collide(KP kp, const void *fin_q, vo
     for (int i = 0; i < 27; ++i) {
         const int cz = czi(i);
         if ((cz < 0 && wall_lo) || (cz > 0 && wall_hi))
-            fout.st(26 - i, n, f[i]);
+            fout.st(26 - i, row, (unsigned)x, f[i]);
         else
-            fout.st(i, nb.at(cxi(i), cyi(i), cz), f[i]);
+            fout.st(i, nb.row(cyi(i), cz), nb.xo(cxi(i)), f[i]);
     }
 }
 
@@ -240,9 +243,10 @@ __global__ __launch_bounds__(kBlock) void k_init(KP kp, const double *rho0, cons
         uz = (real)u0[2 * (size_t)kp.N + n];
     }
     cm_inverse(k, ux, uy, uz);
-    const Pops<P> f(fq, kp.N);
+    const Pops<P> f(fq, kp);
+    const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
 #pragma unroll
-    for (int i = 0; i < 27; ++i) f.st(i, n, k[i]);
+    for (int i = 0; i < 27; ++i) f.st(i, row, x, k[i]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_copy_fluid(KP kp, const double *src, double *dst) {
@@ -360,9 +364,10 @@ __global__ __launch_bounds__(kBlock) void k_get_pop(KP kp, const void *fq, doubl
     if (n >= kp.N) return;
     const unsigned z = n / kp.plane;
     const bool fluid = (int)z >= kp.z0 && (int)z < kp.z1;
-    const Pops<P> f(fq, kp.N);
+    const Pops<P> f(fq, kp);
+    const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
 #pragma unroll
-    for (int i = 0; i < 27; ++i) out[(size_t)i * kp.N + n] = fluid ? (double)f.ld(i, n) : 0.0;
+    for (int i = 0; i < 27; ++i) out[(size_t)i * kp.N + n] = fluid ? (double)f.ld(i, row, x) : 0.0;
 }
 
 template <int P>
@@ -370,9 +375,10 @@ __global__ __launch_bounds__(kBlock) void k_set_pop(KP kp, void *fq, const doubl
     const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
     if (idx >= kp.nfluid) return;
     const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
-    const Pops<P> f(fq, kp.N);
+    const Pops<P> f(fq, kp);
+    const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
 #pragma unroll
-    for (int i = 0; i < 27; ++i) f.st(i, n, (real_t<P>)in[(size_t)i * kp.N + n]);
+    for (int i = 0; i < 27; ++i) f.st(i, row, x, (real_t<P>)in[(size_t)i * kp.N + n]);
 }
 
 // --------------------------------------------------------------------------

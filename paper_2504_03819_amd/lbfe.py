@@ -8,7 +8,7 @@ import ctypes
 import os
 from ctypes import POINTER, byref, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "liblbfe.so")
+LIB_PATH = os.environ.get("LBFE_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "liblbfe.so")
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_DIVERGED, E_STATE = 0, -1, -2, -3, -4, -5
 FP64, FP32, FP16_DEV, FP16_DEV_F0FP32 = 0, 1, 2, 3
