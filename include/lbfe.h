@@ -172,27 +172,43 @@ int lbfe_set_populations(lbfe_ctx *ctx, const double *f_dev);
 int lbfe_reduce(lbfe_ctx *ctx, double out[8]);
 
 /* ---- discrete adjoint (needs params.adjoint = 1) ----------------------- *
- * The adjoint state lambda(t) = dL/df(t) is held in the workspace.  Reverse
- * sweep: lbfe_adjoint_seed at the final time T, then for t = T-1 .. 0
- * lbfe_adjoint_step with the forward state f(t) (raw state as returned by
- * lbfe_get_state), then lbfe_adjoint_init_density for dL/drho0.
- * lbfe_adjoint_grads returns the accumulated parameter gradients. */
+ * Not part of the paper's method: the exact reverse-mode derivative of the
+ * discrete step above (the map f(t) -> f(t+1) of Sec. II B with the wall
+ * treatment of Eqs. (36)-(38)), taking the active branch of the wetting
+ * window and limiter.  The adjoint state lambda(t) = dL/df(t) lives in the
+ * workspace.  Reverse sweep: lbfe_adjoint_seed at the final time T, then for
+ * t = T-1 .. 0 lbfe_adjoint_step with the forward state f(t) (raw state as
+ * from lbfe_get_state, e.g. recomputed from a checkpoint), then
+ * lbfe_adjoint_init_density for dL/drho0.  lbfe_adjoint_grads returns the
+ * accumulated parameter gradients.  All of it is deterministic. */
 
-/* lambda(T)_i(x) = dL/drho(x) for every i (rho = sum_i f_i); resets the
- * parameter-gradient accumulators.  dL_drho_dev: double[nz][ny][nx]. */
+/* lambda(T)_i(x) = dL/drho(x) at every fluid node and for every i (rho is
+ * sum_i f_i); entries at solid nodes are ignored.  Resets the parameter
+ * gradient accumulators.  dL_drho_dev: double[nz][ny][nx]. */
 int lbfe_adjoint_seed(lbfe_ctx *ctx, const double *dL_drho_dev);
 
-/* lambda(t) = (d step / d f(t))^T lambda(t+1), accumulating the parameter
- * gradients; state_t_dev is f(t) at storage precision.  Deterministic. */
+/* General seed: lambda(T) = dL/df(T) given as double[27][nz][ny][nx]
+ * (direction-major like lbfe_get_populations; solid entries ignored).
+ * Resets the parameter-gradient accumulators. */
+int lbfe_adjoint_seed_populations(lbfe_ctx *ctx, const double *dL_df_dev);
+
+/* Current adjoint state lambda(t) decoded to double[27][nz][ny][nx]
+ * (zero at solid nodes). */
+int lbfe_adjoint_get(lbfe_ctx *ctx, double *lambda_dev);
+
+/* lambda(t) = (d step / d f(t))^T lambda(t+1), accumulating dL/dkappa,
+ * dL/d(wet_value) and dL/dnu.  state_t_dev: f(t) at storage precision.
+ * Overwrites the auxiliary fields of the context. */
 int lbfe_adjoint_step(lbfe_ctx *ctx, const void *state_t_dev);
 
-/* Pull lambda(0) back through the initialiser: dL/drho0 into
- * dL_drho0_dev (double[nz][ny][nx], zero at solid nodes), and add the
- * initialiser's kappa / wetting-value contributions to the accumulators. */
-int lbfe_adjoint_init_density(lbfe_ctx *ctx, const double *rho0_dev, double *dL_drho0_dev);
+/* Pull lambda(0) back through the initialiser of lbfe_init_density given
+ * the same rho0_dev and u0_dev (NULL = 0): dL/drho0 into dL_drho0_dev
+ * (double[nz][ny][nx], zero at solid nodes); adds the initialiser's kappa and
+ * wetting-value contributions to the accumulators. */
+int lbfe_adjoint_init_density(lbfe_ctx *ctx, const double *rho0_dev, const double *u0_dev, double *dL_drho0_dev);
 
 /* out[0] = dL/dkappa, out[1] = dL/d(wet_value), out[2] = dL/dnu,
- * out[3] reserved (0).  Host array; synchronises. */
+ * out[3] = 0 (reserved).  Host array; synchronises. */
 int lbfe_adjoint_grads(lbfe_ctx *ctx, double out[4]);
 
 /* Reason for the last error on this context (never NULL). */

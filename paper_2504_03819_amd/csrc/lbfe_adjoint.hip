@@ -1,13 +1,789 @@
-// Discrete adjoint of the D3Q27 free-energy LB step (placeholder).
+// Discrete adjoint of the D3Q27 free-energy LB step: lambda(t) =
+// (d f(t+1) / d f(t))^T lambda(t+1) for the forward map of lbfe_kernels.hip,
+// plus the adjoint of the initialiser and the parameter gradients
+// dL/dkappa, dL/d(wet_value), dL/dnu.  (The adjoint is not part of the
+// paper; it differentiates the paper's discrete update exactly.)
+//
+// Per adjoint step, after the forward auxiliary fields of f(t) have been
+// recomputed (launch_aux):
+//   k_adj_collide   pull-gather lambda*(x) = lambda(t+1)(x + c_i) (or the
+//                   bounce-back slot), local collision adjoint in central-
+//                   moment space; writes the direct part of lambda(t) and
+//                   the adjoints of u, F, Q, p_m (and rho, nu via omega_1)
+//   k_adj_phi       transposed Q stencil -> adjoint of phi; back through
+//                   phi = (p_m - rho/3) u, u = (j + F/2)/rho, F = (1/3-rho) G
+//   k_adj_mu        transposed gradient stencil -> adjoint of mu (all nodes)
+//   k_adj_wall_mu   (walls) wall average of Eq. (36) transposed
+//   k_adj_rho       mu0'(rho) and the (symmetric) Laplacian transposed
+//   k_adj_wall_rho* (walls) limiter/window of Eqs. (37)-(38) transposed
+//   k_adj_final     lambda_i(t) += rho_bar + c_i . j_bar
+//   k_adj_reduce*   deterministic parameter-gradient accumulation
+#include <type_traits>
+
 #include "lbfe_device.h"
 
 namespace lbfe {
-size_t adjoint_aux_bytes(int prec, size_t N) { return 16 * 8 * N; }
-size_t adjoint_grad_slots() { return 4; }
-hipError_t launch_adj_seed(hipStream_t, int, const KP &, const Bufs &, int, const double *) { return hipErrorNotSupported; }
-hipError_t launch_adj_step(hipStream_t, int, const KP &, const Bufs &, int, const void *) { return hipErrorNotSupported; }
-hipError_t launch_adj_init(hipStream_t, int, const KP &, const Bufs &, int, const double *, double *) {
-    return hipErrorNotSupported;
+namespace {
+
+template <int P> using real_t = typename Pol<P>::real;
+
+// Adjoint auxiliary arrays (double, N each) inside Bufs::abuf.
+enum : int {
+    A_UB = 0,    // 3: u_bar
+    A_FB = 3,    // 3: F_bar
+    A_QB = 6,    // 3: Q_bar (after folding the fourth-order terms)
+    A_PMB = 9,   // p_m bar
+    A_RHOB = 10, // rho bar (local part)
+    A_JB = 11,   // 3: j bar
+    A_GB = 14,   // 3: G bar (G = grad mu)
+    A_MUB = 17,  // mu bar (all nodes)
+    A_KAPC = 18, // per-node dL/dkappa contribution
+    A_NUC = 19,  // per-node dL/dnu contribution
+    A_WETC = 20, // per-solid-node dL/d(wet) contribution
+    A_RAVEB = 21,// rho_ave bar at solid nodes
+    A_RHOBT = 22,// rho bar total (all nodes)
+    A_MUBT = 23, // mu bar total (all nodes)
+    A_COUNT = 24
+};
+
+// Adjoint (lambda) storage: same row-blocked layout as the populations, in
+// the compute precision.
+template <class real> struct Lam {
+    real *p;
+    unsigned nx;
+    __device__ Lam(void *q, const KP &kp) : p((real *)q), nx((unsigned)kp.nx) {}
+    __device__ size_t off(int i, unsigned row, unsigned x) const { return ((size_t)row * 27 + i) * nx + x; }
+    __device__ real ld(int i, unsigned row, unsigned x) const { return p[off(i, row, x)]; }
+    __device__ void st(int i, unsigned row, unsigned x, real v) const { p[off(i, row, x)] = v; }
+};
+
+// ---- transposed 1-D transforms -------------------------------------------
+// Transpose of the inverse map (k0,k1,k2) -> (f-,f0,f+) (see inv3).
+template <class real> __device__ inline void inv3_T(real &lm, real &l0, real &lp, real u) {
+    const real s = lp + lm, d = lp - lm;
+    const real k0 = l0 + u * u * ((real)0.5 * s - l0) + (real)0.5 * u * d;
+    const real k1 = u * (s - (real)2 * l0) + (real)0.5 * d;
+    const real k2 = (real)0.5 * s - l0;
+    lm = k0;
+    l0 = k1;
+    lp = k2;
 }
-hipError_t launch_adj_grads(hipStream_t, const KP &, const Bufs &) { return hipErrorNotSupported; }
+// Transpose of the forward map (f-,f0,f+) -> (k0,k1,k2): g_c = m0 + (c-u) m1 + (c-u)^2 m2.
+template <class real> __device__ inline void fwd3_T(real &a, real &b, real &c, real u) {
+    const real m0 = a, m1 = b, m2 = c;
+    const real em = (real)-1 - u, e0 = -u, ep = (real)1 - u;
+    a = m0 + em * m1 + em * em * m2;
+    b = m0 + e0 * m1 + e0 * e0 * m2;
+    c = m0 + ep * m1 + ep * ep * m2;
+}
+// lambda_hat = T(u)^{-T} lambda*  (slots: directions in, central moments out)
+template <class real> __device__ inline void cm_inverse_T(real (&l)[27], real ux, real uy, real uz) {
+#pragma unroll
+    for (int p = 0; p < 9; ++p) inv3_T(l[3 * p], l[3 * p + 1], l[3 * p + 2], uz);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int g = 0; g < 3; ++g) inv3_T(l[9 * a + g], l[9 * a + 3 + g], l[9 * a + 6 + g], uy);
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int g = 0; g < 3; ++g) inv3_T(l[3 * b + g], l[9 + 3 * b + g], l[18 + 3 * b + g], ux);
+}
+// g = T(u)^T m  (slots: central moments in, directions out)
+template <class real> __device__ inline void cm_forward_T(real (&m)[27], real ux, real uy, real uz) {
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+        for (int g = 0; g < 3; ++g) fwd3_T(m[3 * b + g], m[9 + 3 * b + g], m[18 + 3 * b + g], ux);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int g = 0; g < 3; ++g) fwd3_T(m[9 * a + g], m[9 * a + 3 + g], m[9 * a + 6 + g], uy);
+#pragma unroll
+    for (int p = 0; p < 9; ++p) fwd3_T(m[3 * p], m[3 * p + 1], m[3 * p + 2], uz);
+}
+
+// sum_{abg} lam_{abg} (S_x k)_{abg} with (S_x k)_{abg} = a k_{(a-1)bg}; S_y, S_z alike.
+template <class real>
+__device__ inline void shift_dot(const real (&lam)[27], const real (&k)[27], real &sx, real &sy, real &sz) {
+    real ax = 0, ay = 0, az = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int g = 0; g < 3; ++g) {
+                if (a > 0) ax += (real)a * lam[K(a, b, g)] * k[K(a - 1, b, g)];
+                if (b > 0) ay += (real)b * lam[K(a, b, g)] * k[K(a, b - 1, g)];
+                if (g > 0) az += (real)g * lam[K(a, b, g)] * k[K(a, b, g - 1)];
+            }
+    sx = ax;
+    sy = ay;
+    sz = az;
+}
+
+// Transpose of the collision's linear part D (Eqs. (21)-(26) at zero
+// sources), in place on lambda_hat -> D^T lambda_hat, with the adjoints of
+// the sources: F, the six Q terms, p_m and omega_1 (which also multiplies
+// pre-collision moments k).
+template <class real> struct SrcBar {
+    real F[3], Q[6], pm, om1;
+};
+
+template <class real>
+__device__ inline void collide_T(real (&l)[27], const real (&k)[27], const Rates<real> &R, real q200, real q020,
+                                 real q002, SrcBar<real> &sb) {
+    const real one = 1, half = 0.5, third = (real)(1.0 / 3.0), ninth = (real)(1.0 / 9.0);
+    const real *w = R.w;
+    for (int a = 0; a < 3; ++a) sb.F[a] = 0;
+    for (int a = 0; a < 6; ++a) sb.Q[a] = 0;
+    sb.pm = 0;
+    sb.om1 = 0;
+    // first order
+    {
+        const real r0 = one - w[0], c0 = one - half * w[0];
+        sb.F[0] += c0 * l[K(1, 0, 0)];
+        sb.F[1] += c0 * l[K(0, 1, 0)];
+        sb.F[2] += c0 * l[K(0, 0, 1)];
+        l[K(1, 0, 0)] *= r0;
+        l[K(0, 1, 0)] *= r0;
+        l[K(0, 0, 1)] *= r0;
+    }
+    // second order, off-diagonal
+    sb.om1 -= l[K(1, 1, 0)] * k[K(1, 1, 0)] + l[K(0, 1, 1)] * k[K(0, 1, 1)] + l[K(1, 0, 1)] * k[K(1, 0, 1)];
+    l[K(1, 1, 0)] *= (one - w[1]);
+    l[K(0, 1, 1)] *= (one - w[1]);
+    l[K(1, 0, 1)] *= (one - w[1]);
+    // second order, diagonal: (A, B, S) combinations
+    {
+        const real l200 = l[K(2, 0, 0)], l020 = l[K(0, 2, 0)], l002 = l[K(0, 0, 2)];
+        const real Ab = third * (l200 - (real)2 * l020 + l002);
+        const real Bb = third * (l200 + l020 - (real)2 * l002);
+        const real Sb = third * (l200 + l020 + l002);
+        const real A = k[K(2, 0, 0)] - k[K(0, 2, 0)], B = k[K(2, 0, 0)] - k[K(0, 0, 2)];
+        sb.om1 += Ab * (-A - half * (q200 - q020)) + Bb * (-B - half * (q200 - q002));
+        const real c1 = one - half * w[1], c2 = one - half * w[2];
+        sb.Q[0] += c1 * (Ab + Bb) + c2 * Sb;
+        sb.Q[1] += -c1 * Ab + c2 * Sb;
+        sb.Q[2] += -c1 * Bb + c2 * Sb;
+        sb.pm += (real)3 * w[2] * Sb;
+        const real Ap = (one - w[1]) * Ab, Bp = (one - w[1]) * Bb, Sp = (one - w[2]) * Sb;
+        l[K(2, 0, 0)] = Ap + Bp + Sp;
+        l[K(0, 2, 0)] = -Ap + Sp;
+        l[K(0, 0, 2)] = -Bp + Sp;
+    }
+    // third order
+    {
+        const real r3 = one - w[3], r4 = one - w[4], c3 = (one - half * w[3]) * (real)(2.0 / 3.0);
+        auto pair = [&](int ia, int ib, int comp) {
+            const real Pb = half * (l[ia] + l[ib]), Mb = half * (l[ia] - l[ib]);
+            sb.F[comp] += c3 * Pb;
+            l[ia] = r3 * Pb + r4 * Mb;
+            l[ib] = r3 * Pb - r4 * Mb;
+        };
+        pair(K(1, 2, 0), K(1, 0, 2), 0);
+        pair(K(2, 1, 0), K(0, 1, 2), 1);
+        pair(K(2, 0, 1), K(0, 2, 1), 2);
+        l[K(1, 1, 1)] *= (one - w[5]);
+    }
+    // fourth order: (D1, D2, S4) combinations
+    {
+        const real l220 = l[K(2, 2, 0)], l202 = l[K(2, 0, 2)], l022 = l[K(0, 2, 2)];
+        const real D1b = third * (l220 - l202), D2b = third * (l220 - l022), S4b = third * (l220 + l202 + l022);
+        const real c6 = one - half * w[6], c7 = one - half * w[7];
+        sb.Q[3] += c6 * (D1b + D2b) + c7 * S4b;
+        sb.Q[4] += c6 * (-(real)2 * D1b + D2b) + c7 * S4b;
+        sb.Q[5] += c6 * (D1b - (real)2 * D2b) + c7 * S4b;
+        sb.pm += w[7] * S4b;
+        const real D1p = (one - w[6]) * D1b, D2p = (one - w[6]) * D2b, S4p = (one - w[7]) * S4b;
+        l[K(2, 2, 0)] = D1p + D2p + S4p;
+        l[K(2, 0, 2)] = -(real)2 * D1p + D2p + S4p;
+        l[K(0, 2, 2)] = D1p - (real)2 * D2p + S4p;
+        l[K(2, 1, 1)] *= (one - w[8]);
+        l[K(1, 2, 1)] *= (one - w[8]);
+        l[K(1, 1, 2)] *= (one - w[8]);
+    }
+    // fifth order
+    {
+        const real c9 = (one - half * w[9]) * ninth, r9 = one - w[9];
+        sb.F[0] += c9 * l[K(1, 2, 2)];
+        sb.F[1] += c9 * l[K(2, 1, 2)];
+        sb.F[2] += c9 * l[K(2, 2, 1)];
+        l[K(1, 2, 2)] *= r9;
+        l[K(2, 1, 2)] *= r9;
+        l[K(2, 2, 1)] *= r9;
+    }
+    // sixth order
+    sb.pm += w[10] * ninth * l[K(2, 2, 2)];
+    l[K(2, 2, 2)] *= (one - w[10]);
+}
+
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const void *ft, const void *lam_in,
+                                                        void *lam_out) {
+    using real = real_t<P>;
+    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= kp.nfluid) return;
+    const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
+    int x, y, z;
+    decompose(kp, n, x, y, z);
+    const Nb nb(kp, x, y, z);
+    const unsigned row = nb.row(0, 0);
+    const Pops<P> fin(ft, kp);
+    const Lam<real> lin(const_cast<void *>(lam_in), kp), lout(lam_out, kp);
+
+    // forward recomputation at x (identical to k_collide)
+    real k[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) k[i] = fin.ld(i, row, (unsigned)x);
+    double rd;
+    real jx, jy, jz;
+    moments(k, rd, jx, jy, jz);
+    const real *F = (const real *)b.F;
+    const real Fx = F[n], Fy = F[kp.N + n], Fz = F[2 * (size_t)kp.N + n];
+    const real rho = (real)rd;
+    const real ux = (jx + (real)0.5 * Fx) / rho;
+    const real uy = (jy + (real)0.5 * Fy) / rho;
+    const real uz = (jz + (real)0.5 * Fz) / rho;
+    const real pm = (real)((1.0 + b.mu[n]) / 3.0);
+    real q200, q020, q002;
+    q_terms(kp, nb, (const real *)b.phi, q200, q020, q002);
+    real q220 = 0, q202 = 0, q022 = 0;
+    const real third = (real)(1.0 / 3.0);
+    if (kp.corr4) {
+        q220 = (q200 + q020) * third;
+        q202 = (q200 + q002) * third;
+        q022 = (q020 + q002) * third;
+    }
+    Rates<real> R;
+#pragma unroll
+    for (int q = 0; q < 11; ++q) R.w[q] = (real)kp.om[q];
+    const real om1 = (real)1 / (rho * (real)kp.nu / pm + (real)0.5);
+    R.w[1] = om1;
+    cm_forward(k, ux, uy, uz);  // k: pre-collision central moments
+    real ks[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) ks[i] = k[i];
+    collide(ks, R, Fx, Fy, Fz, pm, q200, q020, q002, q220, q202, q022);
+
+    // reverse streaming: lambda*_i(x) = lambda_i(t+1)(x + c_i), or the
+    // bounce-back partner at x when x + c_i is solid
+    const bool wall_lo = kp.walls && z == 1;
+    const bool wall_hi = kp.walls && z == kp.nz - 2;
+    real l[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int cz = czi(i);
+        if ((cz < 0 && wall_lo) || (cz > 0 && wall_hi))
+            l[i] = lin.ld(26 - i, row, (unsigned)x);
+        else
+            l[i] = lin.ld(i, nb.row(cyi(i), cz), nb.xo(cxi(i)));
+    }
+    cm_inverse_T(l, ux, uy, uz);  // l = lambda_hat (adjoint of k*)
+    real ubx, uby, ubz;
+    shift_dot(l, ks, ubx, uby, ubz);  // lambda_hat . S k*
+    SrcBar<real> sb;
+    collide_T(l, k, R, q200, q020, q002, sb);  // l = D^T lambda_hat
+    real tx, ty, tz;
+    shift_dot(l, k, tx, ty, tz);  // (D^T lambda_hat) . S k
+    ubx -= tx;
+    uby -= ty;
+    ubz -= tz;
+    cm_forward_T(l, ux, uy, uz);  // direct part of lambda(t)
+#pragma unroll
+    for (int i = 0; i < 27; ++i) lout.st(i, row, (unsigned)x, l[i]);
+
+    // fold the fourth-order correction (Eq. (28)) into Q_bar
+    real qb0 = sb.Q[0], qb1 = sb.Q[1], qb2 = sb.Q[2];
+    if (kp.corr4) {
+        qb0 += third * (sb.Q[3] + sb.Q[4]);
+        qb1 += third * (sb.Q[3] + sb.Q[5]);
+        qb2 += third * (sb.Q[4] + sb.Q[5]);
+    }
+    // omega_1 = 1 / (rho nu / p_m + 1/2)
+    const double o = (double)om1, dpm = (double)pm, rr = rd;
+    const double om1b = (double)sb.om1;
+    const double rhob = -om1b * o * o * kp.nu / dpm;
+    const double pmb = (double)sb.pm + om1b * o * o * rr * kp.nu / (dpm * dpm);
+    const double nub = -om1b * o * o * rr / dpm;
+    const size_t N = kp.N;
+    double *A = (double *)b.abuf;
+    A[(A_UB + 0) * N + n] = (double)ubx;
+    A[(A_UB + 1) * N + n] = (double)uby;
+    A[(A_UB + 2) * N + n] = (double)ubz;
+    A[(A_FB + 0) * N + n] = (double)sb.F[0];
+    A[(A_FB + 1) * N + n] = (double)sb.F[1];
+    A[(A_FB + 2) * N + n] = (double)sb.F[2];
+    A[(A_QB + 0) * N + n] = (double)qb0;
+    A[(A_QB + 1) * N + n] = (double)qb1;
+    A[(A_QB + 2) * N + n] = (double)qb2;
+    A[A_PMB * N + n] = pmb;
+    A[A_RHOB * N + n] = rhob;
+    A[A_NUC * N + n] = nub;
+}
+
+// phi_bar = transpose of Q_a = -9 sum_i w_i c_ia phi_a(x + c_i), then back
+// through phi = (p_m - rho/3) u, u = (j + F/2)/rho, F = (1/3 - rho) G.
+template <int P> __global__ __launch_bounds__(kBlock) void k_adj_phi(KP kp, Bufs b) {
+    using real = real_t<P>;
+    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= kp.nfluid) return;
+    const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
+    int x, y, z;
+    decompose(kp, n, x, y, z);
+    const Nb nb(kp, x, y, z);
+    const size_t N = kp.N;
+    double *A = (double *)b.abuf;
+    const double *qbx = A + A_QB * N, *qby = A + (A_QB + 1) * N, *qbz = A + (A_QB + 2) * N;
+    double px = 0, py = 0, pz = 0;
+    // transposed stencil: +9 sum_i w_i c_ia Qbar_a(x + c_i)
+#pragma unroll
+    for (int a = -1; a <= 1; ++a)
+#pragma unroll
+        for (int c = -1; c <= 1; ++c) {
+            const double w = w1(a) * w1(c) / 6.0;
+            px += w * (qbx[nb.at(1, a, c)] - qbx[nb.at(-1, a, c)]);
+            py += w * (qby[nb.at(a, 1, c)] - qby[nb.at(a, -1, c)]);
+            pz += w * (qbz[nb.at(a, c, 1)] - qbz[nb.at(a, c, -1)]);
+        }
+    px *= 9.0;
+    py *= 9.0;
+    pz *= 9.0;
+    // forward quantities at x (same arithmetic as k_force)
+    const double r = b.rho[n], mu = b.mu[n];
+    const real *j = (const real *)b.j, *F = (const real *)b.F;
+    const real rr = (real)r;
+    const double Fx = (double)F[n], Fy = (double)F[N + n], Fz = (double)F[2 * N + n];
+    const double ux = (double)((j[n] + (real)0.5 * F[n]) / rr);
+    const double uy = (double)((j[N + n] + (real)0.5 * F[N + n]) / rr);
+    const double uz = (double)((j[2 * N + n] + (real)0.5 * F[2 * N + n]) / rr);
+    const double pm = (1.0 + mu) / 3.0;
+    const double c2 = pm - r / 3.0;
+    double pmb = A[A_PMB * N + n], rhob = A[A_RHOB * N + n];
+    const double pu = px * ux + py * uy + pz * uz;
+    pmb += pu;
+    rhob -= pu / 3.0;
+    const double utx = A[A_UB * N + n] + c2 * px;
+    const double uty = A[(A_UB + 1) * N + n] + c2 * py;
+    const double utz = A[(A_UB + 2) * N + n] + c2 * pz;
+    // u = (j + F/2)/rho
+    A[A_JB * N + n] = utx / r;
+    A[(A_JB + 1) * N + n] = uty / r;
+    A[(A_JB + 2) * N + n] = utz / r;
+    const double Fbx = A[A_FB * N + n] + 0.5 * utx / r;
+    const double Fby = A[(A_FB + 1) * N + n] + 0.5 * uty / r;
+    const double Fbz = A[(A_FB + 2) * N + n] + 0.5 * utz / r;
+    rhob -= (utx * ux + uty * uy + utz * uz) / r;
+    // F = (1/3 - rho) G, G recomputed as in k_force
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        if (i == kRest) continue;
+        const double m = wi(i) * b.mu[nb.at(cxi(i), cyi(i), czi(i))];
+        if (cxi(i)) gx += cxi(i) * m;
+        if (cyi(i)) gy += cyi(i) * m;
+        if (czi(i)) gz += czi(i) * m;
+    }
+    gx *= 3.0;
+    gy *= 3.0;
+    gz *= 3.0;
+    (void)Fx;
+    (void)Fy;
+    (void)Fz;
+    const double c1 = 1.0 / 3.0 - r;
+    A[A_GB * N + n] = c1 * Fbx;
+    A[(A_GB + 1) * N + n] = c1 * Fby;
+    A[(A_GB + 2) * N + n] = c1 * Fbz;
+    rhob -= Fbx * gx + Fby * gy + Fbz * gz;
+    A[A_RHOB * N + n] = rhob;
+    A[A_MUB * N + n] = pmb / 3.0;  // local part of mu_bar (p_m = (1 + mu)/3)
+}
+
+// mu_bar(y) = local part (fluid) - 3 sum_i w_i c_i . G_bar(y + c_i), at every
+// node (G_bar is zero at solid nodes), into A_MUBT.
+__global__ __launch_bounds__(kBlock) void k_adj_mu(KP kp, Bufs b) {
+    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= kp.N) return;
+    int x, y, z;
+    decompose(kp, n, x, y, z);
+    const bool fluid = z >= kp.z0 && z < kp.z1;
+    const Nb nb(kp, x, y, z);
+    const size_t N = kp.N;
+    const double *A = (const double *)b.abuf;
+    const double *gb = A + A_GB * N;
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        if (i == kRest) continue;
+        const unsigned m = nb.at(cxi(i), cyi(i), czi(i));
+        double d = 0.0;
+        if (cxi(i)) d += cxi(i) * gb[m];
+        if (cyi(i)) d += cyi(i) * gb[N + m];
+        if (czi(i)) d += czi(i) * gb[2 * N + m];
+        s += wi(i) * d;
+    }
+    ((double *)b.abuf)[A_MUBT * N + n] = (fluid ? A[A_MUB * N + n] : 0.0) - 3.0 * s;
+}
+
+// Normalising weight sum of the wall average at solid node (x, y, zs).
+__device__ inline double wall_den(const KP &kp, int zs) {
+    double den = 0.0;
+    for (int cz = -1; cz <= 1; ++cz) {
+        const int zz = zs + cz;
+        if (zz < 1 || zz > kp.nz - 2) continue;
+        for (int cy = -1; cy <= 1; ++cy)
+            for (int cx = -1; cx <= 1; ++cx) den += wq(cx, cy, cz);
+    }
+    return den;
+}
+
+// Transpose of a wall average (Eqs. (36)/(37)) for the fluid first layers:
+// dst(y) += sum over solid neighbours s of w(y - s) / den(s) * src(s).
+__global__ __launch_bounds__(kBlock) void k_adj_wall_gather(KP kp, const double *src, double *dst) {
+    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= 2 * kp.plane) return;
+    const int side = idx >= kp.plane;
+    if (side && kp.nz - 2 == 1) return;  // one fluid layer: both walls handled by side 0
+    const unsigned p = idx - (side ? kp.plane : 0u);
+    const int y = (int)(p / (unsigned)kp.nx), x = (int)(p - (unsigned)y * kp.nx);
+    const int zf = side ? kp.nz - 2 : 1;  // fluid layer next to a wall
+    const Nb nb(kp, x, y, zf);
+    double acc = 0.0;
+    for (int cz = -1; cz <= 1; ++cz) {
+        const int zs = zf + cz;
+        if (zs != 0 && zs != kp.nz - 1) continue;  // only solid neighbours
+        const double inv = 1.0 / wall_den(kp, zs);
+        for (int cy = -1; cy <= 1; ++cy)
+            for (int cx = -1; cx <= 1; ++cx) acc += wq(cx, cy, cz) * inv * src[nb.at(cx, cy, cz)];
+    }
+    dst[(size_t)zf * kp.plane + p] += acc;
+}
+
+// rho_bar_total(y) = [fluid: rho_bar + mu_bar mu0'(rho)] - kappa L[mu_bar_fluid](y);
+// per-node dL/dkappa = -mu_bar L[rho].  `mub` is the total mu_bar (solid
+// entries are ignored: the Laplacian's adjoint sees fluid mu_bar only).
+__global__ __launch_bounds__(kBlock) void k_adj_rho(KP kp, Bufs b, const double *mub, const double *rhob_local,
+                                                    const double *rho, double *rhobt, double *kapc) {
+    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= kp.N) return;
+    int x, y, z;
+    decompose(kp, n, x, y, z);
+    const bool fluid = z >= kp.z0 && z < kp.z1;
+    const Nb nb(kp, x, y, z);
+    const double m0 = fluid ? mub[n] : 0.0;
+    const double r0 = rho[n];
+    double lm = 0.0, lr = 0.0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        if (i == kRest) continue;
+        const unsigned m = nb.at(cxi(i), cyi(i), czi(i));
+        const int zz = (int)(m / kp.plane);
+        const bool fl = zz >= kp.z0 && zz < kp.z1;
+        lm += wi(i) * ((fl ? mub[m] : 0.0) - m0);
+        lr += wi(i) * (rho[m] - r0);
+    }
+    lm *= 6.0;
+    lr *= 6.0;
+    double out = -kp.kappa * lm;
+    if (fluid) {
+        const double d = 1.0 - kp.b * r0;
+        const double dmu0 = kp.RT / (r0 * d * d) - 2.0 * kp.a;
+        out += rhob_local[n] + m0 * dmu0;
+        kapc[n] = -m0 * lr;
+    } else {
+        kapc[n] = 0.0;
+    }
+    rhobt[n] = out;
+}
+
+// Solid nodes: rho_ave_bar = W'(rho_ave) rho_bar(x_s), and the per-node
+// dL/d(wet_value) = dW/d(wet) rho_bar(x_s) (active branch of Eq. (38)).
+__global__ __launch_bounds__(kBlock) void k_adj_wall_rho_solid(KP kp, const double *rho, const double *rhobt,
+                                                               double *raveb, double *wetc) {
+    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= 2 * kp.plane) return;
+    const int side = idx >= kp.plane;
+    const unsigned p = idx - (side ? kp.plane : 0u);
+    const int y = (int)(p / (unsigned)kp.nx), x = (int)(p - (unsigned)y * kp.nx);
+    const int zs = side ? kp.nz - 1 : 0;
+    const Nb nb(kp, x, y, zs);
+    double num = 0.0, den = 0.0;
+    for (int cz = -1; cz <= 1; ++cz) {
+        const int zz = zs + cz;
+        if (zz < 1 || zz > kp.nz - 2) continue;
+        for (int cy = -1; cy <= 1; ++cy)
+            for (int cx = -1; cx <= 1; ++cx) {
+                num += wq(cx, cy, cz) * rho[nb.at(cx, cy, cz)];
+                den += wq(cx, cy, cz);
+            }
+    }
+    const double rave = num / den;
+    const size_t n = (size_t)zs * kp.plane + p;
+    const double g = rhobt[n];
+    double dW = 1.0, dwet = 0.0;
+    if (rave >= kp.lo && rave <= kp.hi) {
+        if (kp.wet_mode == LBFE_WET_PHI) {
+            const double v = kp.wet_value * rave;
+            const bool inside = v >= kp.lo && v <= kp.hi;
+            dW = inside ? kp.wet_value : 0.0;
+            dwet = inside ? rave : 0.0;
+        } else if (kp.wet_mode == LBFE_WET_DELTA) {
+            const double v = rave - kp.wet_value;
+            const bool inside = v >= kp.lo && v <= kp.hi;
+            dW = inside ? 1.0 : 0.0;
+            dwet = inside ? -1.0 : 0.0;
+        }
+    }
+    raveb[n] = dW * g;
+    wetc[n] = dwet * g;
+}
+
+// lambda_i(t) = direct part + rho_bar_total + c_i . j_bar at fluid nodes.
+template <int P> __global__ __launch_bounds__(kBlock) void k_adj_final(KP kp, Bufs b, void *lam) {
+    using real = real_t<P>;
+    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= kp.nfluid) return;
+    const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
+    const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
+    const size_t N = kp.N;
+    const double *A = (const double *)b.abuf;
+    const real rb = (real)A[A_RHOBT * N + n];
+    const real jx = (real)A[A_JB * N + n], jy = (real)A[(A_JB + 1) * N + n], jz = (real)A[(A_JB + 2) * N + n];
+    const Lam<real> L(lam, kp);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        real add = rb;
+        if (cxi(i)) add += (real)cxi(i) * jx;
+        if (cyi(i)) add += (real)cyi(i) * jy;
+        if (czi(i)) add += (real)czi(i) * jz;
+        L.st(i, row, x, L.ld(i, row, x) + add);
+    }
+}
+
+// Deterministic accumulation: per-block sums of three per-node arrays, then
+// one block adds them (fixed order) to acc[0..2].
+__global__ __launch_bounds__(kBlock) void k_adj_reduce_part(unsigned n, const double *a0, const double *a1,
+                                                            const double *a2, double *part) {
+    __shared__ double s[3][kBlock];
+    const unsigned i = blockIdx.x * kBlock + threadIdx.x;
+    s[0][threadIdx.x] = (a0 && i < n) ? a0[i] : 0.0;
+    s[1][threadIdx.x] = (a1 && i < n) ? a1[i] : 0.0;
+    s[2][threadIdx.x] = (a2 && i < n) ? a2[i] : 0.0;
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 3; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) part[(size_t)blockIdx.x * 3 + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_reduce_final(unsigned nblk, const double *part, double *acc) {
+    __shared__ double s[3][kBlock];
+    double v[3] = {0, 0, 0};
+    for (unsigned q = threadIdx.x; q < nblk; q += kBlock)
+        for (int k = 0; k < 3; ++k) v[k] += part[(size_t)q * 3 + k];
+    for (int k = 0; k < 3; ++k) s[k][threadIdx.x] = v[k];
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h)
+            for (int k = 0; k < 3; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        acc[0] += s[0][0];  // kappa
+        acc[1] += s[1][0];  // wet value
+        acc[2] += s[2][0];  // nu
+    }
+}
+
+// ---- seed and initialiser ---------------------------------------------------
+template <int P> __global__ __launch_bounds__(kBlock) void k_adj_seed(KP kp, const double *g, void *lam) {
+    using real = real_t<P>;
+    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= kp.N) return;
+    const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
+    const int z = (int)(n / kp.plane);
+    const bool fluid = z >= kp.z0 && z < kp.z1;
+    const real v = fluid ? (real)g[n] : (real)0;
+    const Lam<real> L(lam, kp);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) L.st(i, row, x, v);
+}
+
+template <int P> __global__ __launch_bounds__(kBlock) void k_adj_seed_pop(KP kp, const double *g, void *lam) {
+    using real = real_t<P>;
+    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= kp.N) return;
+    const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
+    const int z = (int)(n / kp.plane);
+    const bool fluid = z >= kp.z0 && z < kp.z1;
+    const Lam<real> L(lam, kp);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) L.st(i, row, x, fluid ? (real)g[(size_t)i * kp.N + n] : (real)0);
+}
+
+template <int P> __global__ __launch_bounds__(kBlock) void k_adj_get(KP kp, const void *lam, double *out) {
+    using real = real_t<P>;
+    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= kp.N) return;
+    const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
+    const int z = (int)(n / kp.plane);
+    const bool fluid = z >= kp.z0 && z < kp.z1;
+    const Lam<real> L(const_cast<void *>(lam), kp);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) out[(size_t)i * kp.N + n] = fluid ? (double)L.ld(i, row, x) : 0.0;
+}
+
+// Initialiser f = T(u0)^{-1} k_eq(rho0, p_m): k_eq_bar = T(u0)^{-T} lambda(0);
+// rho_bar_local = k_eq_bar_000, mu_bar = p_m_bar / 3 (fluid), 0 at solid.
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_adj_init_local(KP kp, Bufs b, const void *lam, const double *u0) {
+    using real = real_t<P>;
+    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= kp.N) return;
+    const int z = (int)(n / kp.plane);
+    const bool fluid = z >= kp.z0 && z < kp.z1;
+    const size_t N = kp.N;
+    double *A = (double *)b.abuf;
+    if (!fluid) {
+        A[A_RHOB * N + n] = 0.0;
+        A[A_MUB * N + n] = 0.0;
+        return;
+    }
+    const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
+    const Lam<real> L(const_cast<void *>(lam), kp);
+    real l[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) l[i] = L.ld(i, row, x);
+    real ux = 0, uy = 0, uz = 0;
+    if (u0) {
+        ux = (real)u0[n];
+        uy = (real)u0[N + n];
+        uz = (real)u0[2 * N + n];
+    }
+    cm_inverse_T(l, ux, uy, uz);
+    const double third = 1.0 / 3.0, ninth = 1.0 / 9.0;
+    const double pmb = (double)l[K(2, 0, 0)] + (double)l[K(0, 2, 0)] + (double)l[K(0, 0, 2)] +
+                       third * ((double)l[K(2, 2, 0)] + (double)l[K(2, 0, 2)] + (double)l[K(0, 2, 2)]) +
+                       ninth * (double)l[K(2, 2, 2)];
+    A[A_RHOB * N + n] = (double)l[K(0, 0, 0)];
+    A[A_MUB * N + n] = pmb / 3.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_init_out(KP kp, const double *rhobt, double *out) {
+    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= kp.N) return;
+    const int z = (int)(n / kp.plane);
+    out[n] = (z >= kp.z0 && z < kp.z1) ? rhobt[n] : 0.0;
+}
+
+template <class Fn> hipError_t dispatch(int prec, Fn &&fn) {
+    switch (prec) {
+        case LBFE_FP64: return fn(std::integral_constant<int, LBFE_FP64>{});
+        case LBFE_FP32: return fn(std::integral_constant<int, LBFE_FP32>{});
+        case LBFE_FP16_DEV: return fn(std::integral_constant<int, LBFE_FP16_DEV>{});
+        default: return fn(std::integral_constant<int, LBFE_FP16_DEV_F0FP32>{});
+    }
+}
+
+// The chain from mu_bar (local parts already in A_MUB, G_bar in A_GB) to
+// rho_bar_total (A_RHOBT) with walls, and the kappa / wet accumulation.
+hipError_t chain_tail(hipStream_t s, const KP &kp, const Bufs &b, bool with_gradient_transpose,
+                      const double *nuc) {
+    const size_t N = kp.N;
+    double *A = (double *)b.abuf;
+    const unsigned gN = nblocks(N), gw = nblocks(2 * (size_t)kp.plane);
+    double *mub_tot = A + A_MUB * N;
+    if (with_gradient_transpose) {
+        k_adj_mu<<<gN, kBlock, 0, s>>>(kp, b);
+        mub_tot = A + A_MUBT * N;
+    }
+    if (kp.walls) k_adj_wall_gather<<<gw, kBlock, 0, s>>>(kp, mub_tot, mub_tot);
+    k_adj_rho<<<gN, kBlock, 0, s>>>(kp, b, mub_tot, A + A_RHOB * N, b.rho, A + A_RHOBT * N, A + A_KAPC * N);
+    const double *wetc = nullptr;
+    if (kp.walls) {
+        k_adj_wall_rho_solid<<<gw, kBlock, 0, s>>>(kp, b.rho, A + A_RHOBT * N, A + A_RAVEB * N, A + A_WETC * N);
+        k_adj_wall_gather<<<gw, kBlock, 0, s>>>(kp, A + A_RAVEB * N, A + A_RHOBT * N);
+        wetc = A + A_WETC * N;
+    }
+    double *part = b.agrad + 8;
+    k_adj_reduce_part<<<gN, kBlock, 0, s>>>((unsigned)N, A + A_KAPC * N, wetc, nuc, part);
+    k_adj_reduce_final<<<1, kBlock, 0, s>>>(gN, part, b.agrad);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t adjoint_aux_bytes(int, size_t N) { return (size_t)A_COUNT * 8 * N; }
+size_t adjoint_grad_slots() { return 3; }
+
+hipError_t launch_adj_seed(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const double *g) {
+    hipError_t e = launch_fill(s, b.agrad, 64);
+    if (e != hipSuccess) return e;
+    // solid-node entries of the adjoint arrays must read as zero
+    e = launch_fill(s, b.abuf, adjoint_aux_bytes(prec, kp.N));
+    if (e != hipSuccess) return e;
+    return dispatch(prec, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        k_adj_seed<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, g, b.lam[lcur]);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_adj_seed_pop(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const double *g) {
+    hipError_t e = launch_fill(s, b.agrad, 64);
+    if (e != hipSuccess) return e;
+    e = launch_fill(s, b.abuf, adjoint_aux_bytes(prec, kp.N));
+    if (e != hipSuccess) return e;
+    return dispatch(prec, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        k_adj_seed_pop<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, g, b.lam[lcur]);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_adj_get(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, double *out) {
+    return dispatch(prec, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        k_adj_get<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, b.lam[lcur], out);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_adj_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const void *ft) {
+    Bufs fb = b;
+    fb.f[0] = const_cast<void *>(ft);
+    hipError_t e = launch_aux(s, prec, kp, fb, 0);
+    if (e != hipSuccess) return e;
+    const unsigned gf = nblocks(kp.nfluid);
+    double *A = (double *)b.abuf;
+    return dispatch(prec, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        k_adj_collide<P><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
+        k_adj_phi<P><<<gf, kBlock, 0, s>>>(kp, b);
+        hipError_t r = chain_tail(s, kp, b, true, A + A_NUC * (size_t)kp.N);
+        if (r != hipSuccess) return r;
+        k_adj_final<P><<<gf, kBlock, 0, s>>>(kp, b, b.lam[1 - lcur]);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_adj_init(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const double *rho0,
+                           const double *u0, double *out) {
+    // forward initialiser quantities: rho (with wall densities) and mu
+    const unsigned gN = nblocks(kp.N);
+    hipError_t e = launch_init_aux(s, kp, b, rho0);
+    if (e != hipSuccess) return e;
+    return dispatch(prec, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        k_adj_init_local<P><<<gN, kBlock, 0, s>>>(kp, b, b.lam[lcur], u0);
+        hipError_t r = chain_tail(s, kp, b, false, nullptr);
+        if (r != hipSuccess) return r;
+        k_adj_init_out<<<gN, kBlock, 0, s>>>(kp, (const double *)b.abuf + A_RHOBT * (size_t)kp.N, out);
+        return hipGetLastError();
+    });
+}
+
 }  // namespace lbfe

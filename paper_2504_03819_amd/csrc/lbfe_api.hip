@@ -137,7 +137,7 @@ Layout layout(const lbfe_params &p) {
         L.lam0 = take(lambda_bytes(p.precision, N));
         L.lam1 = take(lambda_bytes(p.precision, N));
         L.abuf = take(adjoint_aux_bytes(p.precision, N));
-        L.agrad = take(8 * adjoint_grad_slots() * (size_t)nblocks(N));
+        L.agrad = take(8 * (8 + adjoint_grad_slots() * (size_t)nblocks(N)));
     }
     L.total = o;
     return L;
@@ -487,6 +487,29 @@ int lbfe_adjoint_seed(lbfe_ctx *c, const double *dLdrho) {
     return LBFE_OK;
 }
 
+int lbfe_adjoint_seed_populations(lbfe_ctx *c, const double *g) {
+    int r = need_bound(c);
+    if (r) return r;
+    if (!c->p.adjoint) return fail(c, LBFE_E_STATE, "created without params.adjoint = 1");
+    if (!g) return fail(c, LBFE_E_INVAL, "null dL/df");
+    c->lcur = 0;
+    hipError_t e = launch_adj_seed_pop(c->stream, c->p.precision, c->kp, c->b, c->lcur, g);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint_seed_populations");
+    c->adj_seeded = true;
+    return LBFE_OK;
+}
+
+int lbfe_adjoint_get(lbfe_ctx *c, double *out) {
+    int r = need_bound(c);
+    if (r) return r;
+    if (!c->p.adjoint) return fail(c, LBFE_E_STATE, "created without params.adjoint = 1");
+    if (!c->adj_seeded) return fail(c, LBFE_E_STATE, "adjoint not seeded");
+    if (!out) return fail(c, LBFE_E_INVAL, "null output");
+    hipError_t e = launch_adj_get(c->stream, c->p.precision, c->kp, c->b, c->lcur, out);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint_get");
+    return LBFE_OK;
+}
+
 int lbfe_adjoint_step(lbfe_ctx *c, const void *ft) {
     int r = need_bound(c);
     if (r) return r;
@@ -499,13 +522,13 @@ int lbfe_adjoint_step(lbfe_ctx *c, const void *ft) {
     return LBFE_OK;
 }
 
-int lbfe_adjoint_init_density(lbfe_ctx *c, const double *rho0, double *out) {
+int lbfe_adjoint_init_density(lbfe_ctx *c, const double *rho0, const double *u0, double *out) {
     int r = need_bound(c);
     if (r) return r;
     if (!c->p.adjoint) return fail(c, LBFE_E_STATE, "created without params.adjoint = 1");
     if (!c->adj_seeded) return fail(c, LBFE_E_STATE, "adjoint not seeded");
     if (!rho0 || !out) return fail(c, LBFE_E_INVAL, "null rho0 or output");
-    hipError_t e = launch_adj_init(c->stream, c->p.precision, c->kp, c->b, c->lcur, rho0, out);
+    hipError_t e = launch_adj_init(c->stream, c->p.precision, c->kp, c->b, c->lcur, rho0, u0, out);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_init_density");
     return LBFE_OK;
 }
@@ -515,8 +538,7 @@ int lbfe_adjoint_grads(lbfe_ctx *c, double out[4]) {
     if (r) return r;
     if (!c->p.adjoint) return fail(c, LBFE_E_STATE, "created without params.adjoint = 1");
     if (!out) return fail(c, LBFE_E_INVAL, "null output");
-    hipError_t e = launch_adj_grads(c->stream, c->kp, c->b);
-    if (e == hipSuccess) e = hipMemcpyAsync(out, c->b.red, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    hipError_t e = hipMemcpyAsync(out, c->b.agrad, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_grads");
     return LBFE_OK;

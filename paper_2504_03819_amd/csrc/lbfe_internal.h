@@ -43,7 +43,7 @@ struct Bufs {
     // adjoint
     void *lam[2];        // adjoint populations
     void *abuf;          // adjoint auxiliary fields (see adjoint kernels)
-    double *agrad;       // gradient partials
+    double *agrad;       // [4] gradient accumulators, then block partials
 };
 
 // Launchers (lbfe_kernels.hip).  All enqueue on `s` and return hipError_t.
@@ -58,15 +58,18 @@ hipError_t launch_reduce(hipStream_t s, int prec, const KP &kp, const Bufs &b);
 hipError_t launch_get_pop(hipStream_t s, int prec, const KP &kp, const void *f, double *out);
 hipError_t launch_set_pop(hipStream_t s, int prec, const KP &kp, void *f, const double *in);
 hipError_t launch_check_rho0(hipStream_t s, const KP &kp, const double *rho0, int *flag);
+// rho0 (fluid nodes) -> rho with wall densities -> mu, as in the initialiser
+hipError_t launch_init_aux(hipStream_t s, const KP &kp, const Bufs &b, const double *rho0);
 
 // adjoint (lbfe_adjoint.hip)
 size_t adjoint_aux_bytes(int prec, size_t N);
 size_t adjoint_grad_slots();
 hipError_t launch_adj_seed(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const double *dLdrho);
+hipError_t launch_adj_seed_pop(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const double *lam);
+hipError_t launch_adj_get(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, double *out);
 hipError_t launch_adj_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const void *ft);
 hipError_t launch_adj_init(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const double *rho0,
-                           double *out);
-hipError_t launch_adj_grads(hipStream_t s, const KP &kp, const Bufs &b);
+                           const double *u0, double *out);
 
 inline unsigned nblocks(size_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 

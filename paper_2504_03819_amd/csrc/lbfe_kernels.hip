@@ -496,6 +496,14 @@ hipError_t launch_set_pop(hipStream_t s, int prec, const KP &kp, void *f, const 
     });
 }
 
+hipError_t launch_init_aux(hipStream_t s, const KP &kp, const Bufs &b, const double *rho0) {
+    const unsigned gf = nblocks(kp.nfluid), gw = nblocks(2 * (size_t)kp.plane);
+    k_copy_fluid<<<gf, kBlock, 0, s>>>(kp, rho0, b.rho);
+    if (kp.walls) k_wall_rho<<<gw, kBlock, 0, s>>>(kp, b.rho);
+    k_mu<<<gf, kBlock, 0, s>>>(kp, b.rho, b.mu);
+    return hipGetLastError();
+}
+
 hipError_t launch_check_rho0(hipStream_t s, const KP &kp, const double *rho0, int *flag) {
     k_check_rho<<<nblocks(kp.nfluid), kBlock, 0, s>>>(kp, rho0, flag);
     return hipGetLastError();

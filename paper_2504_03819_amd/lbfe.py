@@ -72,7 +72,9 @@ def lib():
         "lbfe_reduce": (c_int, [V, POINTER(c_double)]),
         "lbfe_adjoint_seed": (c_int, [V, V]),
         "lbfe_adjoint_step": (c_int, [V, V]),
-        "lbfe_adjoint_init_density": (c_int, [V, V, V]),
+        "lbfe_adjoint_seed_populations": (c_int, [V, V]),
+        "lbfe_adjoint_get": (c_int, [V, V]),
+        "lbfe_adjoint_init_density": (c_int, [V, V, V, V]),
         "lbfe_adjoint_grads": (c_int, [V, POINTER(c_double)]),
         "lbfe_last_error": (ctypes.c_char_p, [V]),
         "lbfe_destroy": (c_int, [V]),
@@ -245,13 +247,28 @@ class Simulation:
         self._keep_seed = g
         self._check(lib().lbfe_adjoint_seed(self._ctx, _ptr(g)))
 
+    def adjoint_seed_populations(self, dL_df):
+        g = self._dev(dL_df, 27)
+        self._keep_seed = g
+        self._check(lib().lbfe_adjoint_seed_populations(self._ctx, _ptr(g)))
+
+    def adjoint_state(self):
+        out = self._torch.empty((27,) + self.shape, dtype=self._torch.float64, device=self.device)
+        self._check(lib().lbfe_adjoint_get(self._ctx, _ptr(out)))
+        return out
+
     def adjoint_step(self, state_t):
         self._check(lib().lbfe_adjoint_step(self._ctx, _ptr(state_t)))
 
-    def adjoint_init_density(self, rho0=None):
-        rho0 = self._dev(rho0) if rho0 is not None else self._rho0
+    def adjoint_init_density(self, rho0=None, u0=None):
+        """dL/drho0 for the initial state made by init_density (the rho0 and
+        u0 given there are reused unless passed again)."""
+        if rho0 is None:
+            rho0, u0 = self._rho0, self._u0
+        else:
+            rho0, u0 = self._dev(rho0), self._dev(u0, 3)
         out = self._empty()
-        self._check(lib().lbfe_adjoint_init_density(self._ctx, _ptr(rho0), _ptr(out)))
+        self._check(lib().lbfe_adjoint_init_density(self._ctx, _ptr(rho0), _ptr(u0), _ptr(out)))
         return out
 
     def adjoint_grads(self):

@@ -1,0 +1,191 @@
+"""The hand-written discrete adjoint against (1) the oracle's reverse mode
+(torch autograd through the FP64 CPU oracle step), (2) central finite
+differences of the GPU forward path, and (3) itself under different
+checkpoint intervals (bitwise)."""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import DT, droplet_rho, make_sim, oracle_params, rel_err, say
+from oracle import eos, lbm
+from paper_2504_03819_amd import autograd as lag
+from paper_2504_03819_amd import inputs, lbfe
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_vjp(f, lam, p):
+    kappa = torch.tensor(p.kappa, dtype=DT, requires_grad=True)
+    wet = torch.tensor(p.wet_value, dtype=DT, requires_grad=True)
+    nu = torch.tensor(p.nu, dtype=DT, requires_grad=True)
+    pt = dataclasses.replace(p, kappa=kappa, wet_value=wet, nu=nu)
+    fr = f.clone().requires_grad_(True)
+    fn = lbm.step(fr, pt)
+    (fn * lam).sum().backward()
+    gw = float(wet.grad) if wet.grad is not None else 0.0
+    return fr.grad, float(kappa.grad), gw, float(nu.grad)
+
+
+CASES = [
+    ("periodic 7x8x9", (9, 8, 7), False, {}),
+    ("periodic random rates", (8, 8, 8), False,
+     dict(omega=[0.7, 1.0, 1.3, 0.6, 1.8, 1.1, 0.5, 1.9, 0.9, 1.4, 1.2])),
+    ("periodic no corr4", (8, 6, 10), False, dict(corr4=0)),
+    ("walls phi 1.4", (12, 8, 9), True, dict(wet_mode=1, wet_value=1.4)),
+    ("walls drho 1.2", (12, 8, 9), True, dict(wet_mode=2, wet_value=1.2)),
+    ("walls neutral", (10, 7, 8), True, dict(wet_mode=0)),
+]
+
+
+@pytest.mark.parametrize("label,shape,walls,extra", CASES, ids=[c[0] for c in CASES])
+def test_adjoint_step_matches_oracle_reverse_mode(label, shape, walls, extra):
+    say(f"adjoint case {label}")
+    T = eos.temperature(0.7 if walls else 0.85)
+    nz, ny, nx = shape
+    sim = make_sim(nx=nx, ny=ny, nz=nz, T=T, walls_z=int(walls), adjoint=1, **extra)
+    p = oracle_params(sim)
+    rho0 = droplet_rho(shape, T, walls=walls, radius=min(shape) / 3)
+    g = np.random.Generator(np.random.PCG64(31))
+    u0 = 0.03 * g.uniform(-1, 1, (3,) + shape)
+    f0 = lbm.init(torch.tensor(rho0), p, torch.tensor(u0))
+    f = f0 + torch.tensor(inputs.uniform_noise(tuple(f0.shape), 2e-4, 3)) * (f0 != 0)
+    lam = torch.tensor(g.uniform(-1, 1, (27,) + shape))
+    if walls:
+        lam[:, 0] = 0
+        lam[:, -1] = 0
+    sim.set_populations(f)
+    state = sim.get_state().clone()
+    sim.adjoint_seed_populations(lam)
+    sim.adjoint_step(state)
+    lg = sim.adjoint_state().cpu()
+    gg = sim.adjoint_grads()
+    lo, ko, wo, no = _oracle_vjp(f, lam, p)
+    sl = slice(1, -1) if walls else slice(None)
+    e = rel_err(lg[:, sl], lo[:, sl])
+    ek = abs(gg["kappa"] - ko) / max(abs(ko), 1e-300)
+    en = abs(gg["nu"] - no) / max(abs(no), 1e-300)
+    ew = abs(gg["wet_value"] - wo) / max(abs(wo), 1e-12) if walls and p.wet_mode else abs(gg["wet_value"] - wo)
+    say(f"{label}: lambda err={e:.2e} dkappa={gg['kappa']:.6e}/{ko:.6e} ({ek:.1e}) "
+        f"dnu={gg['nu']:.6e}/{no:.6e} ({en:.1e}) dwet={gg['wet_value']:.6e}/{wo:.6e} ({ew:.1e})")
+    assert e < 1e-11
+    assert ek < 1e-9 and en < 1e-9 and ew < 1e-9
+
+
+def _loss_setup(shape, walls, wet_mode, wet_value, steps):
+    T = eos.temperature(0.7)
+    nz, ny, nx = shape
+    rho0 = droplet_rho(shape, T, walls=walls, radius=min(shape) / 3, noise=1e-2, seed=9)
+    rl, rv = eos.maxwell(eos.PAPER["a"], eos.PAPER["b"], eos.PAPER["R"], T)
+    tgt = rho0 + 1e-3 * (rl - rv) * inputs.uniform_noise(shape, 1.0, 12)
+    cfg = lag.StepConfig(nx=nx, ny=ny, nz=nz, steps=steps, checkpoint_every=4, T=T, walls_z=int(walls),
+                         wet_mode=wet_mode)
+    return rho0, tgt, cfg
+
+
+def _gpu_loss(rho0, tgt, cfg, kappa, wet, walls):
+    sim = cfg.make(kappa, wet)
+    sim.init_density(torch.tensor(rho0))
+    sim.step(cfg.steps)
+    r = sim.fields()["rho"].cpu()
+    t = torch.tensor(tgt)
+    sl = slice(1, -1) if walls else slice(None)
+    return float(((r - t)[sl] ** 2).sum())
+
+
+@pytest.mark.parametrize("walls,wet_mode,wet_value", [(False, 0, 1.0), (True, 1, 1.3), (True, 2, 0.6)])
+def test_end_to_end_gradients_vs_oracle_and_fd(walls, wet_mode, wet_value):
+    shape = (10, 8, 8) if walls else (8, 8, 8)
+    steps = 12
+    rho0, tgt, cfg = _loss_setup(shape, walls, wet_mode, wet_value, steps)
+    say(f"end-to-end walls={walls} mode={wet_mode}")
+    # GPU adjoint through the autograd Function
+    r0 = torch.tensor(rho0, device="cuda", requires_grad=True)
+    kap = torch.tensor(0.02, dtype=DT, requires_grad=True)
+    wet = torch.tensor(wet_value, dtype=DT, requires_grad=True)
+    rT = lag.simulate(r0, kap, wet, cfg)
+    sl = slice(1, -1) if walls else slice(None)
+    loss = ((rT - torch.tensor(tgt, device="cuda"))[sl] ** 2).sum()
+    loss.backward()
+    g_r0 = r0.grad.cpu()
+    # oracle reverse mode through init + steps + loss
+    p = lbm.Params(shape[2], shape[1], shape[0], walls_z=walls, T=cfg.T, wet_mode=wet_mode)
+    rl, rv = p.coexistence()
+    ko = torch.tensor(0.02, dtype=DT, requires_grad=True)
+    wo = torch.tensor(wet_value, dtype=DT, requires_grad=True)
+    ro = torch.tensor(rho0, requires_grad=True)
+    po = dataclasses.replace(p, kappa=ko, wet_value=wo, rho_l=rl, rho_v=rv)
+    f = lbm.run(lbm.init(ro, po), po, steps)
+    rho_T = lbm.aux_fields(f, po)["rho"]
+    lo = ((rho_T - torch.tensor(tgt))[sl] ** 2).sum()
+    lo.backward()
+    fl = slice(1, -1) if walls else slice(None)
+    e_r0 = rel_err(g_r0[fl], ro.grad[fl])
+    e_k = abs(float(kap.grad) - float(ko.grad)) / abs(float(ko.grad))
+    say(f"  dL/drho0 err={e_r0:.2e}  dL/dkappa gpu={float(kap.grad):.8e} oracle={float(ko.grad):.8e} ({e_k:.1e})")
+    assert abs(float(loss) - float(lo)) < 1e-10 * float(lo)
+    assert e_r0 < 1e-9 and e_k < 1e-9
+    if walls and wet_mode:
+        e_w = abs(float(wet.grad) - float(wo.grad)) / max(abs(float(wo.grad)), 1e-12)
+        say(f"  dL/dwet gpu={float(wet.grad):.8e} oracle={float(wo.grad):.8e} ({e_w:.1e})")
+        assert e_w < 1e-9
+    # central finite differences of the GPU forward in FP64
+    h = 1e-6
+    fd_k = (_gpu_loss(rho0, tgt, cfg, 0.02 + h, wet_value, walls) -
+            _gpu_loss(rho0, tgt, cfg, 0.02 - h, wet_value, walls)) / (2 * h)
+    say(f"  FD dL/dkappa={fd_k:.8e}")
+    assert abs(fd_k - float(kap.grad)) < 1e-5 * abs(fd_k)
+    if walls and wet_mode:
+        hw = 1e-6
+        fd_w = (_gpu_loss(rho0, tgt, cfg, 0.02, wet_value + hw, walls) -
+                _gpu_loss(rho0, tgt, cfg, 0.02, wet_value - hw, walls)) / (2 * hw)
+        say(f"  FD dL/dwet={fd_w:.8e}")
+        assert abs(fd_w - float(wet.grad)) < 1e-5 * max(abs(fd_w), 1e-8)
+    g = np.random.Generator(np.random.PCG64(4))
+    nodes = [tuple(int(v) for v in (g.integers(1 if walls else 0, shape[0] - (1 if walls else 0)),
+                                    g.integers(0, shape[1]), g.integers(0, shape[2]))) for _ in range(4)]
+    for nd in nodes:
+        rp, rm = rho0.copy(), rho0.copy()
+        rp[nd] += 1e-6
+        rm[nd] -= 1e-6
+        fd = (_gpu_loss(rp, tgt, cfg, 0.02, wet_value, walls) - _gpu_loss(rm, tgt, cfg, 0.02, wet_value, walls)) / 2e-6
+        say(f"  FD dL/drho0{nd}={fd:.8e} adjoint={float(g_r0[nd]):.8e}")
+        assert abs(fd - float(g_r0[nd])) < 1e-5 * max(abs(fd), 1e-6)
+
+
+def test_checkpoint_interval_does_not_change_gradients():
+    shape = (10, 8, 8)
+    rho0, tgt, cfg = _loss_setup(shape, True, 1, 1.3, 9)
+    grads = []
+    for K in (1, 4, 9):
+        cfg.checkpoint_every = K
+        r0 = torch.tensor(rho0, device="cuda", requires_grad=True)
+        kap = torch.tensor(0.02, dtype=DT, requires_grad=True)
+        wet = torch.tensor(1.3, dtype=DT, requires_grad=True)
+        rT = lag.simulate(r0, kap, wet, cfg)
+        ((rT - torch.tensor(tgt, device="cuda"))[1:-1] ** 2).sum().backward()
+        grads.append((r0.grad.cpu().clone(), float(kap.grad), float(wet.grad)))
+    for g in grads[1:]:
+        assert torch.equal(g[0], grads[0][0]) and g[1] == grads[0][1] and g[2] == grads[0][2]
+
+
+def test_fp32_adjoint_close_to_fp64():
+    shape = (12, 10, 10)
+    T = eos.temperature(0.7)
+    rho0 = droplet_rho(shape, T, walls=True, radius=4.0, noise=1e-2, seed=2)
+    out = {}
+    for prec in ("fp64", "fp32"):
+        cfg = lag.StepConfig(nx=10, ny=10, nz=12, steps=20, checkpoint_every=5, T=T, walls_z=1, wet_mode=1,
+                             precision=prec)
+        r0 = torch.tensor(rho0, device="cuda", requires_grad=True)
+        kap = torch.tensor(0.02, dtype=DT, requires_grad=True)
+        wet = torch.tensor(1.3, dtype=DT, requires_grad=True)
+        rT = lag.simulate(r0, kap, wet, cfg)
+        (rT[1:-1] ** 2).sum().backward()
+        out[prec] = (r0.grad.cpu(), float(kap.grad), float(wet.grad))
+    e = rel_err(out["fp32"][0], out["fp64"][0])
+    ek = abs(out["fp32"][1] - out["fp64"][1]) / abs(out["fp64"][1])
+    ew = abs(out["fp32"][2] - out["fp64"][2]) / abs(out["fp64"][2])
+    say(f"fp32 vs fp64 adjoint: drho0 {e:.2e} dkappa {ek:.2e} dwet {ew:.2e}")
+    assert e < 1e-4 and ek < 1e-4 and ew < 1e-4
