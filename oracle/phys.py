@@ -187,8 +187,10 @@ def contact_angle(rho, rho_l, rho_v, z_wall=0.5, zmin_offset=3.0):
                 if a == 0 or a * b < 0:
                     t = a / (a - b)
                     pts.append((h - nh / 2.0, z + t))
-    P = np.array(pts, dtype=np.float64)
+    P = np.array(pts, dtype=np.float64).reshape(-1, 2)
     P = P[P[:, 1] > z_wall + zmin_offset]
+    if len(P) < 3:
+        return float("nan"), float("nan"), float("nan")
     # algebraic circle fit in the (h, z) plane:  h^2 + z^2 + D h + E z + F = 0
     A = np.column_stack([P[:, 0], P[:, 1], np.ones(len(P))])
     rhs = -(P[:, 0] ** 2 + P[:, 1] ** 2)
