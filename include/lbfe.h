@@ -139,9 +139,9 @@ int lbfe_step(lbfe_ctx *ctx, int64_t nsteps);
 /* Timing variant of lbfe_step for benchmarks: the same launches, with HIP
  * events recorded on the context's stream around every kernel;
  * kernel_ms[k] receives the summed milliseconds of kernel class k over the
- * nsteps steps: 0 moments, 1 wall density, 2 mu, 3 wall mu, 4 force,
- * 5 collide-stream.  Synchronises after every step (host array). */
-int lbfe_step_timed(lbfe_ctx *ctx, int64_t nsteps, double kernel_ms[6]);
+ * nsteps steps: 0 moments, 1 wall density, 2 stencil chain (mu, force, Q),
+ * 3 collide-stream.  Synchronises after every step (host array). */
+int lbfe_step_timed(lbfe_ctx *ctx, int64_t nsteps, double kernel_ms[4]);
 
 /* Number of steps taken since lbfe_init_density / lbfe_set_state. */
 int lbfe_step_count(const lbfe_ctx *ctx, int64_t *step);

@@ -247,8 +247,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     const real uy = (jy + (real)0.5 * Fy) / rho;
     const real uz = (jz + (real)0.5 * Fz) / rho;
     const real pm = (real)((1.0 + b.mu[n]) / 3.0);
-    real q200, q020, q002;
-    q_terms(kp, nb, (const real *)b.phi, q200, q020, q002);
+    const real *Qa = (const real *)b.Q;
+    const real q200 = Qa[n], q020 = Qa[kp.N + n], q002 = Qa[2 * (size_t)kp.N + n];
     real q220 = 0, q202 = 0, q022 = 0;
     const real third = (real)(1.0 / 3.0);
     if (kp.corr4) {

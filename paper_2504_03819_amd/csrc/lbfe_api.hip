@@ -111,7 +111,7 @@ std::string validate(const lbfe_params &p) {
 
 // Workspace layout: every sub-buffer 256-byte aligned.
 struct Layout {
-    size_t f0, f1, rho, j, mu, F, phi, flag, part, red, lam0, lam1, abuf, agrad, total;
+    size_t f0, f1, rho, j, mu, F, Q, flag, part, red, lam0, lam1, abuf, agrad, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -129,7 +129,7 @@ Layout layout(const lbfe_params &p) {
     L.j = take(3 * rb * N);
     L.mu = take(8 * N);
     L.F = take(3 * rb * N);
-    L.phi = take(3 * rb * N);
+    L.Q = take(3 * rb * N);
     L.flag = take(256);
     L.part = take(8 * 8 * (size_t)nblocks(nf) + 8 * 8 * (size_t)nblocks(N));
     L.red = take(64);
@@ -283,7 +283,7 @@ int lbfe_bind_workspace(lbfe_ctx *c, void *ws, size_t bytes) {
     c->b.j = w + L.j;
     c->b.mu = (double *)(w + L.mu);
     c->b.F = w + L.F;
-    c->b.phi = w + L.phi;
+    c->b.Q = w + L.Q;
     c->b.flag = (int *)(w + L.flag);
     c->b.part = (double *)(w + L.part);
     c->b.red = (double *)(w + L.red);
@@ -350,26 +350,26 @@ int lbfe_step(lbfe_ctx *c, int64_t nsteps) {
     return LBFE_OK;
 }
 
-int lbfe_step_timed(lbfe_ctx *c, int64_t nsteps, double kernel_ms[6]) {
+int lbfe_step_timed(lbfe_ctx *c, int64_t nsteps, double kernel_ms[4]) {
     int r = need_init(c);
     if (r) return r;
     if (nsteps < 0 || !kernel_ms) return fail(c, LBFE_E_INVAL, "nsteps < 0 or null kernel_ms");
-    hipEvent_t ev[7];
-    for (int k = 0; k < 7; ++k)
+    hipEvent_t ev[5];
+    for (int k = 0; k < 5; ++k)
         if (hipEventCreate(&ev[k]) != hipSuccess) {
             for (int q = 0; q < k; ++q) (void)hipEventDestroy(ev[q]);
             return fail(c, LBFE_E_DEVICE, "hipEventCreate failed");
         }
-    for (int k = 0; k < 6; ++k) kernel_ms[k] = 0.0;
+    for (int k = 0; k < 4; ++k) kernel_ms[k] = 0.0;
     int rc = LBFE_OK;
     for (int64_t s = 0; s < nsteps && rc == LBFE_OK; ++s) {
         hipError_t e = launch_step_timed(c->stream, c->p.precision, c->kp, c->b, c->cur, ev);
-        if (e == hipSuccess) e = hipEventSynchronize(ev[6]);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
         if (e != hipSuccess) {
             rc = hip_fail(c, e, "step_timed");
             break;
         }
-        for (int k = 0; k < 6; ++k) {
+        for (int k = 0; k < 4; ++k) {
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
             kernel_ms[k] += ms;
@@ -377,7 +377,7 @@ int lbfe_step_timed(lbfe_ctx *c, int64_t nsteps, double kernel_ms[6]) {
         c->cur ^= 1;
         c->step++;
     }
-    for (int k = 0; k < 7; ++k) (void)hipEventDestroy(ev[k]);
+    for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
     if (rc == LBFE_OK) {
         int flag = 0;
         if ((rc = read_flag(c, flag))) return rc;

@@ -36,7 +36,7 @@ struct Bufs {
     void *j;             // [3][N] sum_i f_i c_i, compute precision
     double *mu;          // [N] chemical potential (solid: Eq. (36))
     void *F;             // [3][N] force, compute precision
-    void *phi;           // [3][N] (p_m - rho/3) u, compute precision, 0 at solid
+    void *Q;             // [3][N] Q200, Q020, Q002 of Eq. (27), compute precision, 0 at solid
     int *flag;           // divergence / domain flag
     double *part;        // reduction partials [nblk][8]
     double *red;         // final reductions [8]
@@ -52,7 +52,9 @@ hipError_t launch_init(hipStream_t s, int prec, const KP &kp, const Bufs &b, int
                        const double *u0);
 hipError_t launch_aux(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur);
 hipError_t launch_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur);
-hipError_t launch_step_timed(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, hipEvent_t *ev7);
+hipError_t launch_step_timed(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, hipEvent_t *ev5);
+// mu, F and Q of the current rho, j (lbfe_chain.hip)
+hipError_t launch_chain(hipStream_t s, int prec, const KP &kp, const Bufs &b);
 hipError_t launch_export(hipStream_t s, int prec, const KP &kp, const Bufs &b, int which, double *out);
 hipError_t launch_reduce(hipStream_t s, int prec, const KP &kp, const Bufs &b);
 hipError_t launch_get_pop(hipStream_t s, int prec, const KP &kp, const void *f, double *out);

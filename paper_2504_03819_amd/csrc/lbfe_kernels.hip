@@ -1,15 +1,13 @@
 // Forward kernels of the D3Q27 chemical-potential free-energy LB step
 // (arXiv:2504.03819, Sec. II B and Sec. III C) for gfx950.
 //
-// One time step t -> t+1 on the post-streaming state f(t) is five launches:
+// One time step t -> t+1 on the post-streaming state f(t) is four launches:
 //   k_moments   rho (double) and j = sum f c of every fluid node     Eq. (11)
-//   k_wall_rho  density of the solid nodes                      Eqs. (37)-(38)
-//   k_mu        mu = mu0(rho) - kappa lap_h rho                       Eq. (32)
-//   k_wall_mu   mu of the solid nodes                                 Eq. (36)
-//   k_force     F = (1/3 - rho) grad_h mu, u, phi = (p_m - rho/3) u   Eq. (12)
-//   k_collide   Q from phi, CM transform, collision, inverse, push-stream
-//               with halfway bounce-back              Eqs. (10), (21)-(28)
-// (the wall kernels only with solid planes).  Populations are row-blocked
+//   k_wall_rho  density of the solid nodes (walls only)         Eqs. (37)-(38)
+//   k_chain     mu, mu at walls, F, u, phi and Q with LDS-staged
+//               stencils (lbfe_chain.hip)     Eqs. (12), (27), (32), (36)
+//   k_collide   CM transform, collision, inverse, push-stream with halfway
+//               bounce-back                       Eqs. (10), (21)-(26), (28)  Populations are row-blocked
 // (each x-row holds its 27 populations as 27 contiguous runs); one thread per
 // node, x fastest, so every population load and store of a wave64 is one
 // contiguous 64-element run.
@@ -92,16 +90,6 @@ __global__ __launch_bounds__(kBlock) void k_wall_rho(KP kp, double *rho) {
     rho[(size_t)zs * kp.plane + p] = out;
 }
 
-__global__ __launch_bounds__(kBlock) void k_wall_mu(KP kp, double *mu) {
-    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
-    if (idx >= 2 * kp.plane) return;
-    const int side = idx >= kp.plane;
-    const unsigned p = idx - (side ? kp.plane : 0u);
-    const int y = (int)(p / (unsigned)kp.nx), x = (int)(p - (unsigned)y * kp.nx);
-    const int zs = side ? kp.nz - 1 : 0;
-    mu[(size_t)zs * kp.plane + p] = wall_average(kp, mu, x, y, zs);
-}
-
 // mu = mu0(rho) - kappa lap_h rho, lap_h g = 6 sum_i w_i (g(x+c_i) - g(x)).
 __global__ __launch_bounds__(kBlock) void k_mu(KP kp, const double *rho, double *mu) {
     const unsigned idx = tile_id(kp) * kBlock + threadIdx.x;
@@ -120,52 +108,11 @@ __global__ __launch_bounds__(kBlock) void k_mu(KP kp, const double *rho, double 
     mu[n] = mu_bulk(kp, r0) - kp.kappa * 6.0 * s;
 }
 
-// grad_h mu (double), F = (1/3 - rho) grad mu, u = (j + F/2)/rho,
-// phi = (p_m - rho/3) u.
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_force(KP kp, const double *rho, const void *jq, const double *mu, void *Fq,
-                                                  void *phiq) {
-    using real = real_t<P>;
-    const unsigned idx = tile_id(kp) * kBlock + threadIdx.x;
-    if (idx >= kp.nfluid) return;
-    const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
-    int x, y, z;
-    decompose(kp, n, x, y, z);
-    const Nb nb(kp, x, y, z);
-    double gx = 0.0, gy = 0.0, gz = 0.0;
-#pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        if (i == kRest) continue;
-        const double m = wi(i) * mu[nb.at(cxi(i), cyi(i), czi(i))];
-        if (cxi(i)) gx += cxi(i) * m;
-        if (cyi(i)) gy += cyi(i) * m;
-        if (czi(i)) gz += czi(i) * m;
-    }
-    const double r = rho[n];
-    const double c1 = 1.0 / 3.0 - r;
-    const real Fx = (real)(c1 * 3.0 * gx), Fy = (real)(c1 * 3.0 * gy), Fz = (real)(c1 * 3.0 * gz);
-    real *F = (real *)Fq;
-    F[n] = Fx;
-    F[kp.N + n] = Fy;
-    F[2 * (size_t)kp.N + n] = Fz;
-    const real *j = (const real *)jq;
-    const real rr = (real)r;
-    const real ux = (j[n] + (real)0.5 * Fx) / rr;
-    const real uy = (j[kp.N + n] + (real)0.5 * Fy) / rr;
-    const real uz = (j[2 * (size_t)kp.N + n] + (real)0.5 * Fz) / rr;
-    const double pm = (1.0 + mu[n]) / 3.0;
-    const real c2 = (real)(pm - r / 3.0);
-    real *phi = (real *)phiq;
-    phi[n] = c2 * ux;
-    phi[kp.N + n] = c2 * uy;
-    phi[2 * (size_t)kp.N + n] = c2 * uz;
-}
-
 // Fused collide + stream of one fluid node (push: f*_i(x) -> x + c_i, or
 // -> slot opp(i) of x when x + c_i is solid: halfway bounce-back).
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_collide(KP kp, const void *fin_q, void *fout_q, const double *mu,
-                                                    const void *Fq, const void *phiq) {
+                                                    const void *Fq, const void *Qq) {
     using real = real_t<P>;
     const unsigned idx = tile_id(kp) * kBlock + threadIdx.x;
     if (idx >= kp.nfluid) return;
@@ -190,8 +137,8 @@ __global__ __launch_bounds__(kBlock) void k_collide(KP kp, const void *fin_q, vo
     const real uy = (jy + (real)0.5 * Fy) / rho;
     const real uz = (jz + (real)0.5 * Fz) / rho;
     const real pm = (real)((1.0 + mu[n]) / 3.0);
-    real q200, q020, q002;
-    q_terms(kp, nb, (const real *)phiq, q200, q020, q002);
+    const real *Qa = (const real *)Qq;
+    const real q200 = Qa[n], q020 = Qa[kp.N + n], q002 = Qa[2 * (size_t)kp.N + n];
     real q220 = 0, q202 = 0, q022 = 0;
     if (kp.corr4) {  // Eq. (28)
         const real third = (real)(1.0 / 3.0);
@@ -266,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_check_rho(KP kp, const double *rho, 
 // Field export of the current state (aux arrays already evaluated).
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_export(KP kp, int which, const double *rho, const void *jq,
-                                                   const double *mu, const void *Fq, const void *phiq,
+                                                   const double *mu, const void *Fq, const void *Qq,
                                                    double *out) {
     using real = real_t<P>;
     const unsigned n = blockIdx.x * kBlock + threadIdx.x;
@@ -291,12 +238,8 @@ __global__ __launch_bounds__(kBlock) void k_export(KP kp, int which, const doubl
             break;
         }
         case LBFE_FIELD_Q: {
-            real q[3] = {0, 0, 0};
-            if (fluid) {
-                const Nb nb(kp, x, y, z);
-                q_terms(kp, nb, (const real *)phiq, q[0], q[1], q[2]);
-            }
-            for (int a = 0; a < 3; ++a) out[a * N + n] = (double)q[a];
+            const real *Qa = (const real *)Qq;
+            for (int a = 0; a < 3; ++a) out[a * N + n] = fluid ? (double)Qa[a * N + n] : 0.0;
             break;
         }
         default: break;
@@ -383,8 +326,8 @@ __global__ __launch_bounds__(kBlock) void k_set_pop(KP kp, void *fq, const doubl
 
 // --------------------------------------------------------------------------
 // One step's launches.  With `ev` non-null, HIP events are recorded on the
-// stream before the first kernel and after each of the six kernel classes
-// (moments, wall density, mu, wall mu, force, collide-stream).
+// stream before the first kernel and after each of the four kernel classes
+// (moments, wall density, chain, collide-stream).
 template <int P>
 hipError_t aux_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur, hipEvent_t *ev = nullptr) {
     const unsigned gf = nblocks(kp.nfluid), gw = nblocks(2 * (size_t)kp.plane);
@@ -396,12 +339,9 @@ hipError_t aux_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur, hipEven
     mark(1);
     if (kp.walls) k_wall_rho<<<gw, kBlock, 0, s>>>(kp, b.rho);
     mark(2);
-    k_mu<<<gf, kBlock, 0, s>>>(kp, b.rho, b.mu);
+    hipError_t e = launch_chain(s, P, kp, b);
     mark(3);
-    if (kp.walls) k_wall_mu<<<gw, kBlock, 0, s>>>(kp, b.mu);
-    mark(4);
-    k_force<P><<<gf, kBlock, 0, s>>>(kp, b.rho, b.j, b.mu, b.F, b.phi);
-    mark(5);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
@@ -409,8 +349,8 @@ template <int P>
 hipError_t step_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur, hipEvent_t *ev = nullptr) {
     hipError_t e = aux_impl<P>(s, kp, b, cur, ev);
     if (e != hipSuccess) return e;
-    k_collide<P><<<nblocks(kp.nfluid), kBlock, 0, s>>>(kp, b.f[cur], b.f[1 - cur], b.mu, b.F, b.phi);
-    if (ev) (void)hipEventRecord(ev[6], s);
+    k_collide<P><<<nblocks(kp.nfluid), kBlock, 0, s>>>(kp, b.f[cur], b.f[1 - cur], b.mu, b.F, b.Q);
+    if (ev) (void)hipEventRecord(ev[4], s);
     return hipGetLastError();
 }
 
@@ -465,7 +405,7 @@ hipError_t launch_step_timed(hipStream_t s, int prec, const KP &kp, const Bufs &
 hipError_t launch_export(hipStream_t s, int prec, const KP &kp, const Bufs &b, int which, double *out) {
     return dispatch(prec, [&](auto pc) {
         constexpr int P = decltype(pc)::value;
-        k_export<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, which, b.rho, b.j, b.mu, b.F, b.phi, out);
+        k_export<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, which, b.rho, b.j, b.mu, b.F, b.Q, out);
         return hipGetLastError();
     });
 }

@@ -186,12 +186,12 @@ class Simulation:
     def step(self, n=1):
         self._check(lib().lbfe_step(self._ctx, c_int64(int(n))))
 
-    KERNELS = ("moments", "wall_rho", "mu", "wall_mu", "force", "collide_stream")
+    KERNELS = ("moments", "wall_rho", "chain", "collide_stream")
 
     def step_timed(self, n):
         """Run n steps with HIP events around each kernel; returns the summed
         milliseconds per kernel class."""
-        out = (c_double * 6)()
+        out = (c_double * 4)()
         self._check(lib().lbfe_step_timed(self._ctx, c_int64(int(n)), out))
         return dict(zip(self.KERNELS, list(out)))
 
