@@ -107,6 +107,48 @@ def time_form(lbfe, torch, geom, rho, u, form, steps, warmup, timed_steps):
     return out
 
 
+def time_adjoint(lbfe, torch, steps=20, form="fp32"):
+    """Adjoint of the wetting workload (192x192x96, walls, FP32): K forward
+    states are stored, then K adjoint steps are timed (each includes the
+    recomputation of the auxiliary fields of f(t)); the forward recompute
+    that a checkpointed run adds is timed separately."""
+    geom, rho, u, desc = workload("wetting", lbfe, torch)
+    geom = dict(geom, omega=[1.0, 1.0, 1.0, 0.5] + [1.0] * 7)
+    sim = lbfe.Simulation(device="cuda:0", precision=form, adjoint=1, **geom)
+    nfluid = sim.params.nx * sim.params.ny * (sim.params.nz - 2)
+    sim.init_density(torch.tensor(rho))
+    sim.step(50)
+    states = []
+    for _ in range(steps):
+        states.append(sim.get_state().clone())
+        sim.step(1)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sim.adjoint_seed(torch.ones(sim.shape, dtype=torch.float64, device="cuda:0"))
+    torch.cuda.synchronize()
+    e0.record(sim.stream)
+    for t in range(steps - 1, -1, -1):
+        sim.adjoint_step(states[t])
+    e1.record(sim.stream)
+    sim.set_state(states[0], 0)
+    e2.record(sim.stream)
+    sim.step(steps)
+    e3.record(sim.stream)
+    torch.cuda.synchronize()
+    adj_ms = e0.elapsed_time(e1) / steps
+    fwd_ms = e2.elapsed_time(e3) / steps
+    b_alg = 81 * POP_BYTES[form]
+    out = {"workload": desc + ", adjoint, " + form, "mlups_adjoint": nfluid / (adj_ms / 1e3) / 1e6,
+           "mlups_adjoint_with_recompute": nfluid / ((adj_ms + fwd_ms) / 1e3) / 1e6,
+           "ms_per_adjoint_step": adj_ms, "ms_per_forward_recompute": fwd_ms,
+           "alg_bytes_per_node": b_alg,
+           "alg_frac": nfluid * b_alg / (adj_ms / 1e3) / 1e9 / HBM_PEAK_GBS, "steps": steps}
+    sim.close()
+    del states
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(rho, u, geom, seconds_target=20.0):
     """The CPU oracle as it stands, on the full-size workload for a bounded
     number of steps (about 10-30 s of CPU work)."""
@@ -136,6 +178,7 @@ def main():
     ap.add_argument("--forms", default="fp64,fp32,fp16dev,fp16dev_f0fp32")
     ap.add_argument("--timed-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         sys.stderr.write("bench.py: this build runs on one GPU only; a multi-GPU (z-slab) decomposition "
@@ -171,6 +214,10 @@ def main():
         if c.get("source_hash") == kernel_source_hash() and c.get("workload") == args.workload \
                 and c.get("form") == head:
             roof["traffic"] = c.get("bytes_per_launch")
+    adj = None
+    if not args.no_adjoint:
+        print("[bench] timing the adjoint (wetting workload, FP32)", file=sys.stderr, flush=True)
+        adj = time_adjoint(lbfe, torch)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)
@@ -194,6 +241,7 @@ def main():
         "cpu_baseline": cpu,
         "forms": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                   for k, v in results.items()},
+        "adjoint": None if adj is None else {k: (round(v, 4) if isinstance(v, float) else v) for k, v in adj.items()},
         "source_hash": kernel_source_hash(),
     }
     print(json.dumps(line), flush=True)
