@@ -38,11 +38,12 @@ def alg_bytes_per_node(form):
 
 
 def kernel_source_hash():
+    """Hash of the sources the collide-stream kernel is built from (the
+    counter file is ignored once they change)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2504_03819_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, name), "rb").read())
+    for name in ("lbfe_kernels.hip", "lbfe_device.h", "lbfe_internal.h"):
+        h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -169,6 +170,57 @@ def cpu_baseline(rho, u, geom, seconds_target=20.0):
             "kind": "oracle", "sample": f"{steps} full-size steps of the same workload ({dt:.1f} s)"}
 
 
+def copy_calibration(torch, gib=1):
+    """A plain device copy of known size (read gib GiB, write gib GiB): its
+    FETCH_SIZE / WRITE_SIZE counters calibrate the collide kernel's."""
+    n = gib * (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+    torch.cuda.empty_cache()
+
+
+def _read_counter_csv(path, counter):
+    """Per-kernel list of one counter's values (KiB per dispatch) from a
+    rocprofv3 counter_collection.csv."""
+    import csv
+    vals = {}
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            if row.get("Counter_Name") != counter:
+                continue
+            vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return vals
+
+
+def summarize_counters(fetch_csv, write_csv, form, workload_name, out_path):
+    """Calibrated HBM bytes per collide-kernel launch from two rocprofv3
+    --pmc passes (FETCH_SIZE, then WRITE_SIZE) of
+    `bench.py --copy-calib --forms <form> --no-cpu-baseline --no-adjoint`."""
+    fetch_all = _read_counter_csv(fetch_csv, "FETCH_SIZE")
+    write_all = _read_counter_csv(write_csv, "WRITE_SIZE")
+    copy_k = [k for k in fetch_all if "copybuffer" in k.lower()]
+    coll = [k for k in fetch_all if "k_collide" in k]
+    if not copy_k or not coll:
+        raise SystemExit(f"kernels not found: {sorted(fetch_all)}")
+    # the 1 GiB copies are the largest copy dispatches of the run
+    gib_kib = (1 << 30) / 1024.0
+    f_fac = gib_kib / max(max(fetch_all[k]) for k in copy_k)
+    w_fac = gib_kib / max(max(write_all[k]) for k in copy_k if k in write_all)
+    fetch = {k: sum(v) / len(v) for k, v in fetch_all.items()}
+    write = {k: sum(v) / len(v) for k, v in write_all.items()}
+    res = {"form": form, "workload": workload_name, "source_hash": kernel_source_hash(),
+           "fetch_kib_per_launch": fetch[coll[0]], "write_kib_per_launch": write[coll[0]],
+           "copy_fetch_factor": f_fac, "copy_write_factor": w_fac,
+           "bytes_per_launch": (fetch[coll[0]] * f_fac + write[coll[0]] * w_fac) * 1024.0,
+           "kernels": {"fetch_kib": fetch, "write_kib": write}}
+    json.dump(res, open(out_path, "w"), indent=1)
+    print(json.dumps({k: v for k, v in res.items() if k != "kernels"}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,7 +231,13 @@ def main():
     ap.add_argument("--timed-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true", help="run a 1 GiB device copy first (counter calibration)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters, form=args.forms.split(",")[0], workload_name=args.workload,
+                           out_path=COUNTERS)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         sys.stderr.write("bench.py: this build runs on one GPU only; a multi-GPU (z-slab) decomposition "
                          "is designed but not built, so --gpus must be 1.\n")
@@ -191,6 +249,8 @@ def main():
         sys.stderr.write("bench.py needs a GPU\n")
         sys.exit(1)
     geom, rho, u, desc = workload(args.workload, lbfe, torch)
+    if args.copy_calib:
+        copy_calibration(torch)
     forms = [f for f in args.forms.split(",") if f]
     results = {}
     for form in forms:
