@@ -41,9 +41,18 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
     __shared__ double sm[3][NM];
     __shared__ real sp[3][3][NP];
 
+    // Workgroups are dealt round-robin to the 8 XCDs in linear order; the
+    // linear id is remapped so that each XCD runs a contiguous range of
+    // (chunk, tile) pairs, tiles of one chunk consecutively: neighbouring
+    // tiles then share their halo planes through that XCD's L2.
     const int ntx = (kp.nx + TX - 1) / TX;
-    const int x0 = (int)(blockIdx.x % ntx) * TX, y0 = (int)(blockIdx.x / ntx) * TY;
-    const int zs = kp.z0 + (int)blockIdx.y * cz;
+    const unsigned ntiles = gridDim.x, nb = gridDim.x * gridDim.y;
+    const unsigned hw = blockIdx.y * gridDim.x + blockIdx.x;
+    const unsigned q = nb >> 3, rem = nb & 7u, xcd = hw & 7u;
+    const unsigned lid = xcd * q + (xcd < rem ? xcd : rem) + (hw >> 3);
+    const int tile = (int)(lid % ntiles), chunk = (int)(lid / ntiles);
+    const int x0 = (tile % ntx) * TX, y0 = (tile / ntx) * TY;
+    const int zs = kp.z0 + chunk * cz;
     const int ze = min(zs + cz, kp.z1);
     const int tid = threadIdx.x;
     const size_t N = kp.N;
@@ -53,11 +62,11 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
 
     auto fluid = [&](int p) { return kp.walls ? (p >= 1 && p <= kp.nz - 2) : true; };
     auto gplane = [&](int p) { return (size_t)wrap(p, kp.nz) * kp.plane; };
-    // global node of region point (a, b) with halo h, plane p
-    auto gnode = [&](int a, int b, int h, int p) {
-        return gplane(p) + (size_t)wrap(y0 + b - h, kp.ny) * kp.nx + wrap(x0 + a - h, kp.nx);
-    };
     auto interior = [&](int a, int b) { return x0 + a < kp.nx && y0 + b < kp.ny; };
+    // global node of an interior tile point (never wraps)
+    auto inode = [&](int a, int b, int p) {
+        return gplane(p) + (size_t)(y0 + b) * kp.nx + (x0 + a);
+    };
     // wall average of mu over the mu-region ring slot of fluid plane pf into
     // slot of solid plane ps, at region points with halo >= 1
     auto wall_mu = [&](int ps, int pf, bool write_out) {
@@ -72,7 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
                 for (int cx = -1; cx <= 1; ++cx) acc += w1(cx) * w1(cy) * sm[sf][(b + cy) * WM + a + cx];
             sm[ss][r] = acc;
             if (write_out && a >= 3 && b >= 3 && a < TX + 3 && b < TY + 3 && interior(a - 3, b - 3))
-                mu[gnode(a - 3, b - 3, 0, ps)] = acc;
+                mu[inode(a - 3, b - 3, ps)] = acc;
         }
     };
 
@@ -81,14 +90,28 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
     // LDS (rho) or used directly (j, by the thread that owns the point) in
     // iteration k+1.
     constexpr int MR = (NR + kBlock - 1) / kBlock, MP = (NP + kBlock - 1) / kBlock;
+    // In-plane offsets of the region points this thread owns are the same on
+    // every plane: computed once, with the periodic wrap, before the march.
+    unsigned offr[MR], offp[MP];
+#pragma unroll
+    for (int m = 0; m < MR; ++m) {
+        const int r = min(tid + m * kBlock, NR - 1);
+        offr[m] = (unsigned)wrap(y0 + r / WR - 4, kp.ny) * kp.nx + wrap(x0 + r % WR - 4, kp.nx);
+    }
+#pragma unroll
+    for (int m = 0; m < MP; ++m) {
+        const int r = min(tid + m * kBlock, NP - 1);
+        offp[m] = (unsigned)wrap(y0 + r / WP - 1, kp.ny) * kp.nx + wrap(x0 + r % WP - 1, kp.nx);
+    }
     double pr[MR];
     real pj[MP][3];
     auto issue_rho = [&](int p) {
         if (kp.walls && (p < 0 || p > kp.nz - 1)) return;
+        const size_t base = gplane(p);
 #pragma unroll
         for (int m = 0; m < MR; ++m) {
             const int r = tid + m * kBlock;
-            if (r < NR) pr[m] = rho[gnode(r % WR, r / WR, 4, p)];
+            if (r < NR) pr[m] = rho[base + offr[m]];
         }
     };
     auto commit_rho = [&](int p) {
@@ -102,11 +125,12 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
     };
     auto issue_j = [&](int p) {
         if (!fluid(p)) return;
+        const size_t base = gplane(p);
 #pragma unroll
         for (int m = 0; m < MP; ++m) {
             const int r = tid + m * kBlock;
             if (r < NP) {
-                const size_t g = gnode(r % WP, r / WP, 1, p);
+                const size_t g = base + offp[m];
                 pj[m][0] = j[g];
                 pj[m][1] = j[N + g];
                 pj[m][2] = j[2 * N + g];
@@ -149,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
                         const double m = mu_bulk(kp, r0) - kp.kappa * 6.0 * s;
                         sm[sd][r] = m;
                         if (out_plane && a >= 3 && b >= 3 && a < TX + 3 && b < TY + 3 && interior(a - 3, b - 3))
-                            mu[gnode(a - 3, b - 3, 0, p)] = m;
+                            mu[inode(a - 3, b - 3, p)] = m;
                     }
                     if (kp.walls && p == 1) {  // bottom solid plane from the first fluid plane
                         __syncthreads();
@@ -188,7 +212,6 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
                         const double rd = sr[s1][(b + 3) * WR + (a + 3)];
                         const double c1 = 1.0 / 3.0 - rd;
                         const real Fx = (real)(c1 * 3.0 * gx), Fy = (real)(c1 * 3.0 * gy), Fz = (real)(c1 * 3.0 * gz);
-                        const size_t g = gnode(a, b, 1, p);
                         const real rr = (real)rd;
                         const real ux = (cj[m][0] + (real)0.5 * Fx) / rr;
                         const real uy = (cj[m][1] + (real)0.5 * Fy) / rr;
@@ -199,6 +222,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
                         sp[sd][1][r] = c2 * uy;
                         sp[sd][2][r] = c2 * uz;
                         if (out_plane && a >= 1 && b >= 1 && a <= TX && b <= TY && interior(a - 1, b - 1)) {
+                            const size_t g = inode(a - 1, b - 1, p);
                             F[g] = Fx;
                             F[N + g] = Fy;
                             F[2 * N + g] = Fz;
@@ -233,7 +257,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
                             // d_z phi_z: x offset u, y offset v
                             sz += w * (sp[s2][2][c + v * WP + u] - sp[s0][2][c + v * WP + u]);
                         }
-                    const size_t g = gnode(a, b, 0, p);
+                    const size_t g = inode(a, b, p);
                     Q[g] = (real)(-1.5) * sx;
                     Q[N + g] = (real)(-1.5) * sy;
                     Q[2 * N + g] = (real)(-1.5) * sz;
