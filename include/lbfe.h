@@ -70,7 +70,8 @@ extern "C" {
 
 /* Parameters of one simulation (Sec. II B and Sec. III). */
 typedef struct lbfe_params {
-    int64_t nx, ny, nz;  /* lattice size, each >= 1 (nz >= 3 with walls)   */
+    int64_t nx, ny, nz;  /* lattice size, each >= 1 (nz >= 3 with walls),
+                            nx*ny*nz < 2^31, nx*ny <= 2^28                */
     int32_t walls_z;     /* 0 periodic; 1 solid planes z = 0 and z = nz-1  */
     int32_t precision;   /* LBFE_FP64 / FP32 / FP16_DEV / FP16_DEV_F0FP32  */
     double a, b, R, T;   /* van der Waals EOS, Eqs. (29)-(32)              */

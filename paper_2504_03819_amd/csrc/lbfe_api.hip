@@ -87,6 +87,7 @@ std::string validate(const lbfe_params &p) {
     if (p.walls_z && p.nz < 3) return "walls_z needs nz >= 3";
     const double N = (double)p.nx * (double)p.ny * (double)p.nz;
     if (N > 2147483647.0) return "nx*ny*nz must be < 2^31";
+    if ((double)p.nx * (double)p.ny > 268435456.0) return "nx*ny must be <= 2^28";
     if (p.precision < LBFE_FP64 || p.precision > LBFE_FP16_DEV_F0FP32) return "unknown precision";
     if (!(p.a > 0 && p.b > 0 && p.R > 0 && p.T > 0) || !finite(p.a) || !finite(p.b) || !finite(p.R) || !finite(p.T))
         return "a, b, R, T must be finite and > 0";

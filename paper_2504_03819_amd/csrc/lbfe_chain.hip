@@ -4,17 +4,21 @@
 //   mu   -> G = grad_h mu, F = (1/3 - rho) G,               (Eq. (12))
 //           u = (j + F/2)/rho, phi = (p_m - rho/3) u
 //   phi  -> Q_aa = -3 d_a phi_a                              (Eq. (27))
-// Each workgroup owns a TX x TY column tile and marches in z over a chunk
-// of planes.  Three plane rings live in LDS: rho on the tile with a 4-node
-// halo, mu with 3, phi with 1, so every neighbour read of the three
-// 27-point stencils is an LDS read and each plane of rho is read from
-// global memory once per tile.  mu is evaluated on a 2-node halo, or on the
-// full 3-node halo next to a solid plane, whose wall average (Eq. (36)) is
-// then needed on a 2-node halo.  The z-pipeline of iteration k loads
-// rho(k+3), evaluates mu(k+2), then F, phi at k+1 and Q at k; the first
-// chunk planes are recomputed as the pipeline fills.
-// Outputs per fluid node: mu (double), F and Q (compute precision); mu is
-// also written at the solid planes.
+//
+// Each workgroup owns a TX x TY column tile and marches in z over a chunk of
+// planes.  The isotropic D3Q27 stencils factor into D1Q3 pieces (weights
+// 1/6, 2/3, 1/6 along each axis), so every stencil is evaluated as an
+// in-plane part, read from one LDS plane, and a z part, combined in a
+// three-plane register ring that each thread keeps for the columns it owns:
+//   lap_h g = 6 (Wz (Wx Wy g) - g)
+//   d_x g   = 1/2 Wz (Dx Wy g),  d_y g = 1/2 Wz (Wx Dy g),  d_z g = 1/2 Dz (Wx Wy g)
+// with W the D1Q3 weights and D g = g(+1) - g(-1).  LDS holds a ring of three
+// rho planes (tile + 4-node halo), two mu planes (3-node halo) and one phi
+// plane (1-node halo).  Iteration k of the march loads rho(k+3), evaluates
+// mu(k+2) and the in-plane parts of mu(k+2), then F and phi at k+1 and the
+// in-plane parts of phi(k+1), and Q at k; global loads run one iteration
+// ahead.  Outputs per fluid node: mu (double), F and Q (compute precision);
+// mu is also written at the solid planes.
 #include <type_traits>
 
 #include "lbfe_device.h"
@@ -26,6 +30,33 @@ constexpr int TX = 16, TY = 16;
 constexpr int WR = TX + 8, HR = TY + 8, NR = WR * HR;  // rho region (halo 4)
 constexpr int WM = TX + 6, HM = TY + 6, NM = WM * HM;  // mu region (halo 3)
 constexpr int WP = TX + 2, HP = TY + 2, NP = WP * HP;  // phi region (halo 1)
+constexpr int MR = (NR + kBlock - 1) / kBlock;         // rho points per thread
+constexpr int MM = (NM + kBlock - 1) / kBlock;         // mu points per thread
+constexpr int MP = (NP + kBlock - 1) / kBlock;         // phi points per thread
+constexpr double A1 = 1.0 / 6.0, A0 = 2.0 / 3.0;       // D1Q3 weights
+
+// Branch-free global access: raw buffer loads/stores through a descriptor
+// of one plane; masked lanes use an offset past the plane, which the
+// hardware drops (stores) or reads as zero (loads).  Keeping every global
+// access outside lane-divergent branches lets the compiler count outstanding
+// memory operations instead of draining them all at each plane.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr unsigned kOOB = 0x80000000u;
+__device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
+}
+__device__ inline void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+__device__ inline void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+__device__ inline void bload(double &v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ inline void bload(float &v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+    v = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
 
 __device__ inline int wrap(int v, int n) {
     v %= n;
@@ -33,13 +64,22 @@ __device__ inline int wrap(int v, int n) {
 }
 __device__ inline int slot3(int p) { return ((p % 3) + 3) % 3; }
 
+// Wx Wy g of the 3x3 in-plane neighbourhood of index c in a row-major LDS
+// plane with row stride W.
+template <int W> __device__ inline double smooth2(const double *g, int c) {
+    const double r0 = A1 * g[c - W - 1] + A0 * g[c - W] + A1 * g[c - W + 1];
+    const double r1 = A1 * g[c - 1] + A0 * g[c] + A1 * g[c + 1];
+    const double r2 = A1 * g[c + W - 1] + A0 * g[c + W] + A1 * g[c + W + 1];
+    return A1 * r0 + A0 * r1 + A1 * r2;
+}
+
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restrict__ rho, const void *jq,
                                                   double *__restrict__ mu, void *Fq, void *Qq, int cz) {
     using real = typename Pol<P>::real;
     __shared__ double sr[3][NR];
-    __shared__ double sm[3][NM];
-    __shared__ real sp[3][3][NP];
+    __shared__ double sm[2][NM];
+    __shared__ real sp[3][NP];
 
     // Workgroups are dealt round-robin to the 8 XCDs in linear order; the
     // linear id is remapped so that each XCD runs a contiguous range of
@@ -61,211 +101,246 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
     real *Q = (real *)Qq;
 
     auto fluid = [&](int p) { return kp.walls ? (p >= 1 && p <= kp.nz - 2) : true; };
+    auto valid = [&](int p) { return !kp.walls || (p >= 0 && p <= kp.nz - 1); };
     auto gplane = [&](int p) { return (size_t)wrap(p, kp.nz) * kp.plane; };
     auto interior = [&](int a, int b) { return x0 + a < kp.nx && y0 + b < kp.ny; };
-    // global node of an interior tile point (never wraps)
-    auto inode = [&](int a, int b, int p) {
-        return gplane(p) + (size_t)(y0 + b) * kp.nx + (x0 + a);
-    };
-    // wall average of mu over the mu-region ring slot of fluid plane pf into
-    // slot of solid plane ps, at region points with halo >= 1
-    auto wall_mu = [&](int ps, int pf, bool write_out) {
-        const int ss = slot3(ps), sf = slot3(pf);
-        for (int r = tid; r < NM; r += kBlock) {
-            const int a = r % WM, b = r / WM;
-            if (a < 1 || a > WM - 2 || b < 1 || b > HM - 2) continue;
-            double acc = 0.0;
-#pragma unroll
-            for (int cy = -1; cy <= 1; ++cy)
-#pragma unroll
-                for (int cx = -1; cx <= 1; ++cx) acc += w1(cx) * w1(cy) * sm[sf][(b + cy) * WM + a + cx];
-            sm[ss][r] = acc;
-            if (write_out && a >= 3 && b >= 3 && a < TX + 3 && b < TY + 3 && interior(a - 3, b - 3))
-                mu[inode(a - 3, b - 3, ps)] = acc;
-        }
-    };
+    auto inode = [&](int a, int b, int p) { return gplane(p) + (size_t)(y0 + b) * kp.nx + (x0 + a); };
 
-    // Global loads run one iteration ahead: rho(k+4) and j(k+2) are issued
-    // into registers while iteration k computes from LDS, and committed to
-    // LDS (rho) or used directly (j, by the thread that owns the point) in
-    // iteration k+1.
-    constexpr int MR = (NR + kBlock - 1) / kBlock, MP = (NP + kBlock - 1) / kBlock;
-    // In-plane offsets of the region points this thread owns are the same on
-    // every plane: computed once, with the periodic wrap, before the march.
+    // in-plane byte offsets of the owned rho-region and phi-region points
+    // (kOOB for lanes past the region)
     unsigned offr[MR], offp[MP];
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
-        const int r = min(tid + m * kBlock, NR - 1);
-        offr[m] = (unsigned)wrap(y0 + r / WR - 4, kp.ny) * kp.nx + wrap(x0 + r % WR - 4, kp.nx);
+        const int r = tid + m * kBlock;
+        offr[m] = r < NR ? 8u * ((unsigned)wrap(y0 + r / WR - 4, kp.ny) * kp.nx + wrap(x0 + r % WR - 4, kp.nx)) : kOOB;
     }
 #pragma unroll
     for (int m = 0; m < MP; ++m) {
-        const int r = min(tid + m * kBlock, NP - 1);
-        offp[m] = (unsigned)wrap(y0 + r / WP - 1, kp.ny) * kp.nx + wrap(x0 + r % WP - 1, kp.nx);
+        const int r = tid + m * kBlock;
+        offp[m] = r < NP ? (unsigned)sizeof(real) *
+                               ((unsigned)wrap(y0 + r / WP - 1, kp.ny) * kp.nx + wrap(x0 + r % WP - 1, kp.nx))
+                         : kOOB;
     }
+    const unsigned pbytes8 = kp.plane * 8u, pbytesr = kp.plane * (unsigned)sizeof(real);
+    // byte offset of an interior tile point inside its plane, or kOOB
+    auto ioff = [&](bool ok, int a, int b, unsigned esize) {
+        return ok ? esize * ((unsigned)(y0 + b) * kp.nx + (x0 + a)) : kOOB;
+    };
+
     double pr[MR];
-    real pj[MP][3];
+    real pj[MP][3], cj[MP][3];
+    // loads of every plane index are issued (planes outside a walled box
+    // wrap to valid memory and their values are never used)
     auto issue_rho = [&](int p) {
-        if (kp.walls && (p < 0 || p > kp.nz - 1)) return;
-        const size_t base = gplane(p);
+        const __amdgpu_buffer_rsrc_t rr = plane_rsrc(rho + gplane(p), pbytes8);
 #pragma unroll
-        for (int m = 0; m < MR; ++m) {
-            const int r = tid + m * kBlock;
-            if (r < NR) pr[m] = rho[base + offr[m]];
-        }
+        for (int m = 0; m < MR; ++m) bload(pr[m], rr, offr[m]);
     };
     auto commit_rho = [&](int p) {
-        if (kp.walls && (p < 0 || p > kp.nz - 1)) return;
+        if (!valid(p)) return;
         const int s = slot3(p);
 #pragma unroll
-        for (int m = 0; m < MR; ++m) {
-            const int r = tid + m * kBlock;
-            if (r < NR) sr[s][r] = pr[m];
-        }
+        for (int m = 0; m < MR; ++m)
+            if (tid + m * kBlock < NR) sr[s][tid + m * kBlock] = pr[m];
     };
     auto issue_j = [&](int p) {
-        if (!fluid(p)) return;
         const size_t base = gplane(p);
 #pragma unroll
-        for (int m = 0; m < MP; ++m) {
-            const int r = tid + m * kBlock;
-            if (r < NP) {
-                const size_t g = base + offp[m];
-                pj[m][0] = j[g];
-                pj[m][1] = j[N + g];
-                pj[m][2] = j[2 * N + g];
-            }
+        for (int c = 0; c < 3; ++c) {
+            const __amdgpu_buffer_rsrc_t rj = plane_rsrc(j + c * N + base, pbytesr);
+#pragma unroll
+            for (int m = 0; m < MP; ++m) bload(pj[m][c], rj, offp[m]);
         }
     };
-    real cj[MP][3];  // j of the plane stage C works on
+
+    // register rings, index 0/1/2 = planes p-1, p, p+1 of the consumer
+    double Pr[MM][3];                        // Wx Wy rho at owned mu points
+    double Ar[MP][3], Br[MP][3], Cr[MP][3];  // Dx Wy mu, Wx Dy mu, Wx Wy mu at owned phi points
+    real Xr[3], Yr[3], Zr[3];                // in-plane parts of the Q stencils at the tile point
+#pragma unroll
+    for (int m = 0; m < MM; ++m) Pr[m][0] = Pr[m][1] = Pr[m][2] = 0.0;
+#pragma unroll
+    for (int m = 0; m < MP; ++m)
+#pragma unroll
+        for (int t = 0; t < 3; ++t) Ar[m][t] = Br[m][t] = Cr[m][t] = 0.0;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) Xr[t] = Yr[t] = Zr[t] = (real)0;
+#pragma unroll
+    for (int m = 0; m < MR; ++m) pr[m] = 0.0;
+#pragma unroll
+    for (int m = 0; m < MP; ++m)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pj[m][c] = cj[m][c] = (real)0;
+
+    // wall average (Eq. (36)) of mu plane pf into mu plane ps, on the points
+    // with a halo of at most 2
+    auto wall_mu = [&](int ps, int pf, bool write_out) {
+        const int ss = ps & 1, sf = pf & 1;
+        for (int r = tid; r < NM; r += kBlock) {
+            const int a = r % WM, b = r / WM;
+            if (a < 1 || a > WM - 2 || b < 1 || b > HM - 2) continue;
+            const double v = smooth2<WM>(sm[sf], r);
+            sm[ss][r] = v;
+            if (write_out && a >= 3 && b >= 3 && a < TX + 3 && b < TY + 3 && interior(a - 3, b - 3))
+                mu[inode(a - 3, b - 3, ps)] = v;
+        }
+    };
+    // in-plane parts of grad mu from mu plane p at the owned phi point m
+    auto abc = [&](int p, int m, double &Av, double &Bv, double &Cv) {
+        const int r = tid + m * kBlock;
+        const int c = (r / WP + 2) * WM + (r % WP + 2);
+        const double *g = sm[p & 1];
+        const double l0 = g[c - WM - 1], l1 = g[c - WM], l2 = g[c - WM + 1];
+        const double m0 = g[c - 1], m1 = g[c], m2 = g[c + 1];
+        const double h0 = g[c + WM - 1], h1 = g[c + WM], h2 = g[c + WM + 1];
+        Av = A1 * (l2 - l0) + A0 * (m2 - m0) + A1 * (h2 - h0);
+        Bv = A1 * (h0 - l0) + A0 * (h1 - l1) + A1 * (h2 - l2);
+        Cv = A1 * (A1 * l0 + A0 * l1 + A1 * l2) + A0 * (A1 * m0 + A0 * m1 + A1 * m2) +
+             A1 * (A1 * h0 + A0 * h1 + A1 * h2);
+    };
 
     issue_rho(zs - 3);
     for (int k = zs - 6; k < ze; ++k) {
-        // A: commit rho(k+3) (halo-4 region); take j(k+1); prefetch the next
+        // ---- A: commit rho(k+3); take j(k+1); prefetch rho(k+4), j(k+2)
         commit_rho(k + 3);
 #pragma unroll
         for (int m = 0; m < MP; ++m)
+#pragma unroll
             for (int c = 0; c < 3; ++c) cj[m][c] = pj[m][c];
         __syncthreads();
         issue_rho(k + 4);
-        if (k + 2 >= zs - 1) issue_j(k + 2);
-        // B: mu(k+2) on the halo-2 (or halo-3) region
+        issue_j(k + 2);
+
+        // ---- B: Wx Wy rho(k+3) on the mu region; mu(k+2)
         {
-            const int p = k + 2;
-            if (p >= zs - 2) {
-                const bool out_plane = (p >= zs && p < ze) || (kp.walls && (p == zs - 1 || p == ze) && !fluid(p));
-                if (fluid(p)) {
-                    const int s0 = slot3(p - 1), s1 = slot3(p), s2 = slot3(p + 1), sd = slot3(p);
-                    // full 3-node halo only where a wall average follows
-                    const bool full = kp.walls && (p == 1 || p == kp.nz - 2);
-                    for (int r = tid; r < NM; r += kBlock) {
-                        const int a = r % WM, b = r / WM;
-                        if (!full && (a < 1 || a > WM - 2 || b < 1 || b > HM - 2)) continue;
-                        const int c = (b + 1) * WR + (a + 1);  // same point in the rho region
-                        const double r0 = sr[s1][c];
-                        double s = 0.0;
+            const int q3 = k + 3, p = k + 2;
+            const bool pv = valid(q3);
+            const int s3 = slot3(q3), s2 = slot3(p);
+            const bool do_mu = p >= zs - 2 && fluid(p);
+            const bool out_plane = p >= zs && p < ze;
+            const bool full = kp.walls && (p == 1 || p == kp.nz - 2);
+            const __amdgpu_buffer_rsrc_t rmu = plane_rsrc(mu + gplane(p), pbytes8);
 #pragma unroll
-                        for (int i = 0; i < 27; ++i) {
-                            if (i == kRest) continue;
-                            const int ss = czi(i) < 0 ? s0 : (czi(i) > 0 ? s2 : s1);
-                            s += wi(i) * (sr[ss][c + cyi(i) * WR + cxi(i)] - r0);
-                        }
-                        const double m = mu_bulk(kp, r0) - kp.kappa * 6.0 * s;
-                        sm[sd][r] = m;
-                        if (out_plane && a >= 3 && b >= 3 && a < TX + 3 && b < TY + 3 && interior(a - 3, b - 3))
-                            mu[inode(a - 3, b - 3, p)] = m;
+            for (int m = 0; m < MM; ++m) {
+                const int r = tid + m * kBlock;
+                Pr[m][0] = Pr[m][1];
+                Pr[m][1] = Pr[m][2];
+                const int a = r % WM, b = r / WM;
+                double v = 0.0;
+                bool out = false;
+                if (r < NM) {
+                    const int c = (b + 1) * WR + (a + 1);  // the same point in the rho region
+                    if (pv) Pr[m][2] = smooth2<WR>(sr[s3], c);
+                    if (do_mu && (full || (a >= 1 && a <= WM - 2 && b >= 1 && b <= HM - 2))) {
+                        const double r0 = sr[s2][c];
+                        const double s27 = A1 * Pr[m][0] + A0 * Pr[m][1] + A1 * Pr[m][2];
+                        v = mu_bulk(kp, r0) - kp.kappa * 6.0 * (s27 - r0);
+                        sm[p & 1][r] = v;
+                        out = out_plane && a >= 3 && b >= 3 && a < TX + 3 && b < TY + 3 && interior(a - 3, b - 3);
                     }
-                    if (kp.walls && p == 1) {  // bottom solid plane from the first fluid plane
-                        __syncthreads();
-                        wall_mu(0, 1, zs - 1 == 0);
-                    }
-                } else if (kp.walls && p == kp.nz - 1) {  // top solid plane
-                    wall_mu(p, p - 1, out_plane);
                 }
+                bstore(v, rmu, ioff(out, a - 3, b - 3, 8u));
+            }
+            if (kp.walls && p == 1 && p >= zs - 2) {  // bottom solid plane, from the first fluid plane
+                __syncthreads();
+                wall_mu(0, 1, zs - 1 == 0);
+            } else if (kp.walls && p == kp.nz - 1 && p >= zs - 2) {  // top solid plane
+                wall_mu(p, p - 1, p == ze);
             }
         }
         __syncthreads();
-        // C: F, phi at k+1 on the halo-1 region
+
+        // ---- C: in-plane parts of mu(k+2); F and phi at k+1
         {
-            const int p = k + 1;
-            if (p >= zs - 1) {
-                const int sd = slot3(p);
-                if (fluid(p)) {
-                    const int s0 = slot3(p - 1), s1 = slot3(p), s2 = slot3(p + 1);
-                    const bool out_plane = p >= zs && p < ze;
+            const int p2 = k + 2, p1 = k + 1;
+            const bool do_abc = p2 >= zs - 2 && valid(p2);
+            const bool do_phi = p1 >= zs - 1;
+            const bool fl1 = fluid(p1);
+            const bool out_plane = p1 >= zs && p1 < ze;
+            const size_t base1 = gplane(p1);
+            const __amdgpu_buffer_rsrc_t rF0 = plane_rsrc(F + base1, pbytesr);
+            const __amdgpu_buffer_rsrc_t rF1 = plane_rsrc(F + N + base1, pbytesr);
+            const __amdgpu_buffer_rsrc_t rF2 = plane_rsrc(F + 2 * N + base1, pbytesr);
 #pragma unroll
-                    for (int m = 0; m < MP; ++m) {
-                        const int r = tid + m * kBlock;
-                        if (r >= NP) continue;
-                        const int a = r % WP, b = r / WP;
-                        const int cm = (b + 2) * WM + (a + 2);  // point in the mu region
-                        double gx = 0.0, gy = 0.0, gz = 0.0;
-#pragma unroll
-                        for (int i = 0; i < 27; ++i) {
-                            if (i == kRest) continue;
-                            const int ss = czi(i) < 0 ? s0 : (czi(i) > 0 ? s2 : s1);
-                            const double m = wi(i) * sm[ss][cm + cyi(i) * WM + cxi(i)];
-                            if (cxi(i)) gx += cxi(i) * m;
-                            if (cyi(i)) gy += cyi(i) * m;
-                            if (czi(i)) gz += czi(i) * m;
-                        }
-                        const double rd = sr[s1][(b + 3) * WR + (a + 3)];
+            for (int m = 0; m < MP; ++m) {
+                const int r = tid + m * kBlock;
+                Ar[m][0] = Ar[m][1];
+                Ar[m][1] = Ar[m][2];
+                Br[m][0] = Br[m][1];
+                Br[m][1] = Br[m][2];
+                Cr[m][0] = Cr[m][1];
+                Cr[m][1] = Cr[m][2];
+                const int a = r % WP, b = r / WP;
+                real Fx = 0, Fy = 0, Fz = 0;
+                bool out = false;
+                if (r < NP) {
+                    if (do_abc) abc(p2, m, Ar[m][2], Br[m][2], Cr[m][2]);
+                    // the bottom solid plane's mu only exists from the step
+                    // that evaluated the first fluid plane: refresh its entry
+                    if (do_abc && kp.walls && p2 == 1) abc(0, m, Ar[m][1], Br[m][1], Cr[m][1]);
+                    if (do_phi && !fl1) sp[0][r] = sp[1][r] = sp[2][r] = (real)0;
+                    if (do_phi && fl1) {
+                        const double gx = 0.5 * (A1 * Ar[m][0] + A0 * Ar[m][1] + A1 * Ar[m][2]);
+                        const double gy = 0.5 * (A1 * Br[m][0] + A0 * Br[m][1] + A1 * Br[m][2]);
+                        const double gz = 0.5 * (Cr[m][2] - Cr[m][0]);
+                        const double rd = sr[slot3(p1)][(b + 3) * WR + (a + 3)];
                         const double c1 = 1.0 / 3.0 - rd;
-                        const real Fx = (real)(c1 * 3.0 * gx), Fy = (real)(c1 * 3.0 * gy), Fz = (real)(c1 * 3.0 * gz);
+                        Fx = (real)(c1 * gx);
+                        Fy = (real)(c1 * gy);
+                        Fz = (real)(c1 * gz);
                         const real rr = (real)rd;
                         const real ux = (cj[m][0] + (real)0.5 * Fx) / rr;
                         const real uy = (cj[m][1] + (real)0.5 * Fy) / rr;
                         const real uz = (cj[m][2] + (real)0.5 * Fz) / rr;
-                        const double pm = (1.0 + sm[s1][cm]) / 3.0;
+                        const double pm = (1.0 + sm[p1 & 1][(b + 2) * WM + (a + 2)]) / 3.0;
                         const real c2 = (real)(pm - rd / 3.0);
-                        sp[sd][0][r] = c2 * ux;
-                        sp[sd][1][r] = c2 * uy;
-                        sp[sd][2][r] = c2 * uz;
-                        if (out_plane && a >= 1 && b >= 1 && a <= TX && b <= TY && interior(a - 1, b - 1)) {
-                            const size_t g = inode(a - 1, b - 1, p);
-                            F[g] = Fx;
-                            F[N + g] = Fy;
-                            F[2 * N + g] = Fz;
-                        }
+                        sp[0][r] = c2 * ux;
+                        sp[1][r] = c2 * uy;
+                        sp[2][r] = c2 * uz;
+                        out = out_plane && a >= 1 && b >= 1 && a <= TX && b <= TY && interior(a - 1, b - 1);
                     }
-                } else {
-                    for (int r = tid; r < NP; r += kBlock) sp[sd][0][r] = sp[sd][1][r] = sp[sd][2][r] = (real)0;
                 }
+                const unsigned o = ioff(out, a - 1, b - 1, (unsigned)sizeof(real));
+                bstore(Fx, rF0, o);
+                bstore(Fy, rF1, o);
+                bstore(Fz, rF2, o);
             }
         }
         __syncthreads();
-        // D: Q at k on the tile
+
+        // ---- D: in-plane parts of phi(k+1); Q at k
         {
-            const int p = k;
-            if (p >= zs && fluid(p)) {
-                const int s0 = slot3(p - 1), s1 = slot3(p), s2 = slot3(p + 1);
-                for (int r = tid; r < TX * TY; r += kBlock) {
-                    const int a = r % TX, b = r / TX;
-                    if (!interior(a, b)) continue;
-                    const int c = (b + 1) * WP + (a + 1);
-                    real sx = 0, sy = 0, sz = 0;
-#pragma unroll
-                    for (int u = -1; u <= 1; ++u)
-#pragma unroll
-                        for (int v = -1; v <= 1; ++v) {
-                            const real w = (real)(w1(u) * w1(v));
-                            // d_x phi_x: y offset u, z offset v
-                            const int sv = v < 0 ? s0 : (v > 0 ? s2 : s1);
-                            sx += w * (sp[sv][0][c + u * WP + 1] - sp[sv][0][c + u * WP - 1]);
-                            // d_y phi_y: x offset u, z offset v
-                            sy += w * (sp[sv][1][c + WP + u] - sp[sv][1][c - WP + u]);
-                            // d_z phi_z: x offset u, y offset v
-                            sz += w * (sp[s2][2][c + v * WP + u] - sp[s0][2][c + v * WP + u]);
-                        }
-                    const size_t g = inode(a, b, p);
-                    Q[g] = (real)(-1.5) * sx;
-                    Q[N + g] = (real)(-1.5) * sy;
-                    Q[2 * N + g] = (real)(-1.5) * sz;
-                }
+            const int p1 = k + 1, p0 = k;
+            Xr[0] = Xr[1];
+            Xr[1] = Xr[2];
+            Yr[0] = Yr[1];
+            Yr[1] = Yr[2];
+            Zr[0] = Zr[1];
+            Zr[1] = Zr[2];
+            const int a = tid % TX, b = tid / TX;
+            const int c = (b + 1) * WP + (a + 1);
+            const real w1r = (real)A1, w0r = (real)A0;
+            if (p1 >= zs - 1) {
+                const real *gx = sp[0], *gy = sp[1], *gz = sp[2];
+                Xr[2] = w1r * (gx[c - WP + 1] - gx[c - WP - 1]) + w0r * (gx[c + 1] - gx[c - 1]) +
+                        w1r * (gx[c + WP + 1] - gx[c + WP - 1]);
+                Yr[2] = w1r * (gy[c + WP - 1] - gy[c - WP - 1]) + w0r * (gy[c + WP] - gy[c - WP]) +
+                        w1r * (gy[c + WP + 1] - gy[c - WP + 1]);
+                Zr[2] = w1r * (w1r * gz[c - WP - 1] + w0r * gz[c - WP] + w1r * gz[c - WP + 1]) +
+                        w0r * (w1r * gz[c - 1] + w0r * gz[c] + w1r * gz[c + 1]) +
+                        w1r * (w1r * gz[c + WP - 1] + w0r * gz[c + WP] + w1r * gz[c + WP + 1]);
+            }
+            {
+                const real h = (real)(-1.5);
+                const size_t base0 = gplane(p0);
+                const unsigned o = ioff(p0 >= zs && fluid(p0) && interior(a, b), a, b, (unsigned)sizeof(real));
+                bstore(h * (w1r * Xr[0] + w0r * Xr[1] + w1r * Xr[2]), plane_rsrc(Q + base0, pbytesr), o);
+                bstore(h * (w1r * Yr[0] + w0r * Yr[1] + w1r * Yr[2]), plane_rsrc(Q + N + base0, pbytesr), o);
+                bstore(h * (Zr[2] - Zr[0]), plane_rsrc(Q + 2 * N + base0, pbytesr), o);
             }
         }
-        // no barrier here: the next writes to the phi ring (stage C of k+1)
-        // come after two barriers
+        // no barrier: the next writes to the phi plane (stage C of k+1) and
+        // to the mu ring (stage B of k+1) come after at least one barrier
     }
 }
 
