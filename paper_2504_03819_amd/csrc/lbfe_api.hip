@@ -112,7 +112,7 @@ std::string validate(const lbfe_params &p) {
 
 // Workspace layout: every sub-buffer 256-byte aligned.
 struct Layout {
-    size_t f0, f1, rho, j, mu, F, Q, flag, part, red, lam0, lam1, abuf, agrad, total;
+    size_t f0, f1, rho, j, mu, mu0, F, Q, flag, part, red, lam0, lam1, abuf, agrad, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -129,6 +129,7 @@ Layout layout(const lbfe_params &p) {
     L.rho = take(8 * N);
     L.j = take(3 * rb * N);
     L.mu = take(8 * N);
+    L.mu0 = take(8 * N);
     L.F = take(3 * rb * N);
     L.Q = take(3 * rb * N);
     L.flag = take(256);
@@ -283,6 +284,7 @@ int lbfe_bind_workspace(lbfe_ctx *c, void *ws, size_t bytes) {
     c->b.rho = (double *)(w + L.rho);
     c->b.j = w + L.j;
     c->b.mu = (double *)(w + L.mu);
+    c->b.mu0 = (double *)(w + L.mu0);
     c->b.F = w + L.F;
     c->b.Q = w + L.Q;
     c->b.flag = (int *)(w + L.flag);

@@ -1,5 +1,6 @@
 // The stencil chain of one step on gfx950, one kernel:
-//   rho  -> mu = mu0(rho) - kappa lap_h rho                 (Eq. (32))
+//   rho  -> mu = mu0 - kappa lap_h rho                      (Eq. (32))
+//           (mu0 = mu0(rho) per node comes from the moments kernel)
 //        -> solid-node mu by the wall average              (Eq. (36))
 //   mu   -> G = grad_h mu, F = (1/3 - rho) G,               (Eq. (12))
 //           u = (j + F/2)/rho, phi = (p_m - rho/3) u
@@ -16,8 +17,8 @@
 // rho planes (tile + 4-node halo), two mu planes (3-node halo) and one phi
 // plane (1-node halo).  Iteration k of the march loads rho(k+3), evaluates
 // mu(k+2) and the in-plane parts of mu(k+2), then F and phi at k+1 and the
-// in-plane parts of phi(k+1), and Q at k; global loads run one iteration
-// ahead.  Outputs per fluid node: mu (double), F and Q (compute precision);
+// in-plane parts of phi(k+1), and Q at k; global loads run ahead of their
+// use.  Outputs per fluid node: mu (double), F and Q (compute precision);
 // mu is also written at the solid planes.
 #include <type_traits>
 
@@ -26,13 +27,14 @@
 namespace lbfe {
 namespace {
 
-constexpr int TX = 16, TY = 16;
+constexpr int TX = 32, TY = 16;
+constexpr int CB = TX * TY;                            // threads: one per tile column
 constexpr int WR = TX + 8, HR = TY + 8, NR = WR * HR;  // rho region (halo 4)
 constexpr int WM = TX + 6, HM = TY + 6, NM = WM * HM;  // mu region (halo 3)
 constexpr int WP = TX + 2, HP = TY + 2, NP = WP * HP;  // phi region (halo 1)
-constexpr int MR = (NR + kBlock - 1) / kBlock;         // rho points per thread
-constexpr int MM = (NM + kBlock - 1) / kBlock;         // mu points per thread
-constexpr int MP = (NP + kBlock - 1) / kBlock;         // phi points per thread
+constexpr int MR = (NR + CB - 1) / CB;         // rho points per thread
+constexpr int MM = (NM + CB - 1) / CB;         // mu points per thread
+constexpr int MP = (NP + CB - 1) / CB;         // phi points per thread
 constexpr double A1 = 1.0 / 6.0, A0 = 2.0 / 3.0;       // D1Q3 weights
 
 // Branch-free global access: raw buffer loads/stores through a descriptor
@@ -74,8 +76,8 @@ template <int W> __device__ inline double smooth2(const double *g, int c) {
 }
 
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restrict__ rho, const void *jq,
-                                                  double *__restrict__ mu, void *Fq, void *Qq, int cz) {
+__global__ __launch_bounds__(CB) void k_chain(KP kp, const double *__restrict__ rho, const double *__restrict__ mu0,
+                                              const void *jq, double *__restrict__ mu, void *Fq, void *Qq, int cz) {
     using real = typename Pol<P>::real;
     __shared__ double sr[3][NR];
     __shared__ double sm[2][NM];
@@ -102,21 +104,27 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
 
     auto fluid = [&](int p) { return kp.walls ? (p >= 1 && p <= kp.nz - 2) : true; };
     auto valid = [&](int p) { return !kp.walls || (p >= 0 && p <= kp.nz - 1); };
-    auto gplane = [&](int p) { return (size_t)wrap(p, kp.nz) * kp.plane; };
     auto interior = [&](int a, int b) { return x0 + a < kp.nx && y0 + b < kp.ny; };
-    auto inode = [&](int a, int b, int p) { return gplane(p) + (size_t)(y0 + b) * kp.nx + (x0 + a); };
+    // plane indices wrap periodically; inside the march they advance by one
+    auto next = [&](int g) { return g + 1 == kp.nz ? 0 : g + 1; };
+    auto pbase = [&](int g) { return (size_t)g * kp.plane; };
 
-    // in-plane byte offsets of the owned rho-region and phi-region points
+    // in-plane byte offsets of the owned rho-, mu- and phi-region points
     // (kOOB for lanes past the region)
-    unsigned offr[MR], offp[MP];
+    unsigned offr[MR], offm[MM], offp[MP];
 #pragma unroll
     for (int m = 0; m < MR; ++m) {
-        const int r = tid + m * kBlock;
+        const int r = tid + m * CB;
         offr[m] = r < NR ? 8u * ((unsigned)wrap(y0 + r / WR - 4, kp.ny) * kp.nx + wrap(x0 + r % WR - 4, kp.nx)) : kOOB;
     }
 #pragma unroll
+    for (int m = 0; m < MM; ++m) {
+        const int r = tid + m * CB;
+        offm[m] = r < NM ? 8u * ((unsigned)wrap(y0 + r / WM - 3, kp.ny) * kp.nx + wrap(x0 + r % WM - 3, kp.nx)) : kOOB;
+    }
+#pragma unroll
     for (int m = 0; m < MP; ++m) {
-        const int r = tid + m * kBlock;
+        const int r = tid + m * CB;
         offp[m] = r < NP ? (unsigned)sizeof(real) *
                                ((unsigned)wrap(y0 + r / WP - 1, kp.ny) * kp.nx + wrap(x0 + r % WP - 1, kp.nx))
                          : kOOB;
@@ -127,30 +135,37 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
         return ok ? esize * ((unsigned)(y0 + b) * kp.nx + (x0 + a)) : kOOB;
     };
 
-    double pr[MR];
-    real pj[MP][3], cj[MP][3];
-    // loads of every plane index are issued (planes outside a walled box
-    // wrap to valid memory and their values are never used)
-    auto issue_rho = [&](int p) {
-        const __amdgpu_buffer_rsrc_t rr = plane_rsrc(rho + gplane(p), pbytes8);
+    // Global loads run ahead of their use: rho one iteration ahead, mu0 and
+    // j issued right after the stage that consumed the previous plane.
+    // Loads of every plane index are issued (planes outside a walled box
+    // wrap to valid memory and their values are never used).
+    double pr[MR], m0[MM];
+    real pj[MP][3];
+    auto issue_rho = [&](int g) {
+        const __amdgpu_buffer_rsrc_t rr = plane_rsrc(rho + pbase(g), pbytes8);
 #pragma unroll
         for (int m = 0; m < MR; ++m) bload(pr[m], rr, offr[m]);
     };
-    auto commit_rho = [&](int p) {
-        if (!valid(p)) return;
-        const int s = slot3(p);
+    auto issue_mu0 = [&](int g) {
+        const __amdgpu_buffer_rsrc_t rr = plane_rsrc(mu0 + pbase(g), pbytes8);
 #pragma unroll
-        for (int m = 0; m < MR; ++m)
-            if (tid + m * kBlock < NR) sr[s][tid + m * kBlock] = pr[m];
+        for (int m = 0; m < MM; ++m) bload(m0[m], rr, offm[m]);
     };
-    auto issue_j = [&](int p) {
-        const size_t base = gplane(p);
+    auto issue_j = [&](int g) {
+        const size_t base = pbase(g);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const __amdgpu_buffer_rsrc_t rj = plane_rsrc(j + c * N + base, pbytesr);
 #pragma unroll
             for (int m = 0; m < MP; ++m) bload(pj[m][c], rj, offp[m]);
         }
+    };
+    auto commit_rho = [&](int p) {
+        if (!valid(p)) return;
+        const int s = slot3(p);
+#pragma unroll
+        for (int m = 0; m < MR; ++m)
+            if (tid + m * CB < NR) sr[s][tid + m * CB] = pr[m];
     };
 
     // register rings, index 0/1/2 = planes p-1, p, p+1 of the consumer
@@ -165,29 +180,23 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
         for (int t = 0; t < 3; ++t) Ar[m][t] = Br[m][t] = Cr[m][t] = 0.0;
 #pragma unroll
     for (int t = 0; t < 3; ++t) Xr[t] = Yr[t] = Zr[t] = (real)0;
-#pragma unroll
-    for (int m = 0; m < MR; ++m) pr[m] = 0.0;
-#pragma unroll
-    for (int m = 0; m < MP; ++m)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) pj[m][c] = cj[m][c] = (real)0;
 
     // wall average (Eq. (36)) of mu plane pf into mu plane ps, on the points
     // with a halo of at most 2
     auto wall_mu = [&](int ps, int pf, bool write_out) {
         const int ss = ps & 1, sf = pf & 1;
-        for (int r = tid; r < NM; r += kBlock) {
+        for (int r = tid; r < NM; r += CB) {
             const int a = r % WM, b = r / WM;
             if (a < 1 || a > WM - 2 || b < 1 || b > HM - 2) continue;
             const double v = smooth2<WM>(sm[sf], r);
             sm[ss][r] = v;
             if (write_out && a >= 3 && b >= 3 && a < TX + 3 && b < TY + 3 && interior(a - 3, b - 3))
-                mu[inode(a - 3, b - 3, ps)] = v;
+                mu[pbase(ps) + (size_t)(y0 + b - 3) * kp.nx + (x0 + a - 3)] = v;
         }
     };
     // in-plane parts of grad mu from mu plane p at the owned phi point m
     auto abc = [&](int p, int m, double &Av, double &Bv, double &Cv) {
-        const int r = tid + m * kBlock;
+        const int r = tid + m * CB;
         const int c = (r / WP + 2) * WM + (r % WP + 2);
         const double *g = sm[p & 1];
         const double l0 = g[c - WM - 1], l1 = g[c - WM], l2 = g[c - WM + 1];
@@ -199,17 +208,17 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
              A1 * (A1 * h0 + A0 * h1 + A1 * h2);
     };
 
-    issue_rho(zs - 3);
+    // wrapped indices of planes k, k+1, k+2, k+3, k+4
+    int g0 = wrap(zs - 6, kp.nz);
+    int g1 = next(g0), g2 = next(g1), g3 = next(g2), g4 = next(g3);
+    issue_rho(g3);      // rho(zs - 3)
+    issue_mu0(g2);      // mu0(zs - 4)
+    issue_j(g1);        // j(zs - 5)
     for (int k = zs - 6; k < ze; ++k) {
-        // ---- A: commit rho(k+3); take j(k+1); prefetch rho(k+4), j(k+2)
+        // ---- A: commit rho(k+3); prefetch rho(k+4)
         commit_rho(k + 3);
-#pragma unroll
-        for (int m = 0; m < MP; ++m)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) cj[m][c] = pj[m][c];
         __syncthreads();
-        issue_rho(k + 4);
-        issue_j(k + 2);
+        issue_rho(g4);
 
         // ---- B: Wx Wy rho(k+3) on the mu region; mu(k+2)
         {
@@ -219,10 +228,10 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
             const bool do_mu = p >= zs - 2 && fluid(p);
             const bool out_plane = p >= zs && p < ze;
             const bool full = kp.walls && (p == 1 || p == kp.nz - 2);
-            const __amdgpu_buffer_rsrc_t rmu = plane_rsrc(mu + gplane(p), pbytes8);
+            const __amdgpu_buffer_rsrc_t rmu = plane_rsrc(mu + pbase(g2), pbytes8);
 #pragma unroll
             for (int m = 0; m < MM; ++m) {
-                const int r = tid + m * kBlock;
+                const int r = tid + m * CB;
                 Pr[m][0] = Pr[m][1];
                 Pr[m][1] = Pr[m][2];
                 const int a = r % WM, b = r / WM;
@@ -234,13 +243,14 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
                     if (do_mu && (full || (a >= 1 && a <= WM - 2 && b >= 1 && b <= HM - 2))) {
                         const double r0 = sr[s2][c];
                         const double s27 = A1 * Pr[m][0] + A0 * Pr[m][1] + A1 * Pr[m][2];
-                        v = mu_bulk(kp, r0) - kp.kappa * 6.0 * (s27 - r0);
+                        v = m0[m] - kp.kappa * 6.0 * (s27 - r0);
                         sm[p & 1][r] = v;
                         out = out_plane && a >= 3 && b >= 3 && a < TX + 3 && b < TY + 3 && interior(a - 3, b - 3);
                     }
                 }
                 bstore(v, rmu, ioff(out, a - 3, b - 3, 8u));
             }
+            issue_mu0(g3);
             if (kp.walls && p == 1 && p >= zs - 2) {  // bottom solid plane, from the first fluid plane
                 __syncthreads();
                 wall_mu(0, 1, zs - 1 == 0);
@@ -257,13 +267,13 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
             const bool do_phi = p1 >= zs - 1;
             const bool fl1 = fluid(p1);
             const bool out_plane = p1 >= zs && p1 < ze;
-            const size_t base1 = gplane(p1);
+            const size_t base1 = pbase(g1);
             const __amdgpu_buffer_rsrc_t rF0 = plane_rsrc(F + base1, pbytesr);
             const __amdgpu_buffer_rsrc_t rF1 = plane_rsrc(F + N + base1, pbytesr);
             const __amdgpu_buffer_rsrc_t rF2 = plane_rsrc(F + 2 * N + base1, pbytesr);
 #pragma unroll
             for (int m = 0; m < MP; ++m) {
-                const int r = tid + m * kBlock;
+                const int r = tid + m * CB;
                 Ar[m][0] = Ar[m][1];
                 Ar[m][1] = Ar[m][2];
                 Br[m][0] = Br[m][1];
@@ -288,12 +298,12 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
                         Fx = (real)(c1 * gx);
                         Fy = (real)(c1 * gy);
                         Fz = (real)(c1 * gz);
-                        const real rr = (real)rd;
-                        const real ux = (cj[m][0] + (real)0.5 * Fx) / rr;
-                        const real uy = (cj[m][1] + (real)0.5 * Fy) / rr;
-                        const real uz = (cj[m][2] + (real)0.5 * Fz) / rr;
-                        const double pm = (1.0 + sm[p1 & 1][(b + 2) * WM + (a + 2)]) / 3.0;
-                        const real c2 = (real)(pm - rd / 3.0);
+                        const real ir = (real)1 / (real)rd;
+                        const real ux = (pj[m][0] + (real)0.5 * Fx) * ir;
+                        const real uy = (pj[m][1] + (real)0.5 * Fy) * ir;
+                        const real uz = (pj[m][2] + (real)0.5 * Fz) * ir;
+                        // p_m - rho/3 with p_m = (1 + mu)/3
+                        const real c2 = (real)((1.0 + sm[p1 & 1][(b + 2) * WM + (a + 2)] - rd) * (1.0 / 3.0));
                         sp[0][r] = c2 * ux;
                         sp[1][r] = c2 * uy;
                         sp[2][r] = c2 * uz;
@@ -305,6 +315,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
                 bstore(Fy, rF1, o);
                 bstore(Fz, rF2, o);
             }
+            issue_j(g2);
         }
         __syncthreads();
 
@@ -332,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
             }
             {
                 const real h = (real)(-1.5);
-                const size_t base0 = gplane(p0);
+                const size_t base0 = pbase(g0);
                 const unsigned o = ioff(p0 >= zs && fluid(p0) && interior(a, b), a, b, (unsigned)sizeof(real));
                 bstore(h * (w1r * Xr[0] + w0r * Xr[1] + w1r * Xr[2]), plane_rsrc(Q + base0, pbytesr), o);
                 bstore(h * (w1r * Yr[0] + w0r * Yr[1] + w1r * Yr[2]), plane_rsrc(Q + N + base0, pbytesr), o);
@@ -341,6 +352,11 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
         }
         // no barrier: the next writes to the phi plane (stage C of k+1) and
         // to the mu ring (stage B of k+1) come after at least one barrier
+        g0 = g1;
+        g1 = g2;
+        g2 = g3;
+        g3 = g4;
+        g4 = next(g4);
     }
 }
 
@@ -351,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_chain(KP kp, const double *__restric
 static int chain_chunk(const KP &kp, unsigned tiles) {
     const int nzf = kp.z1 - kp.z0;
     int cz = 32;
-    while (cz > 8 && (size_t)tiles * ((nzf + cz - 1) / cz) < 2048) cz /= 2;
+    while (cz > 8 && (size_t)tiles * ((nzf + cz - 1) / cz) * CB < 2048 * 256) cz /= 2;
     return cz;
 }
 
@@ -361,10 +377,10 @@ hipError_t launch_chain(hipStream_t s, int prec, const KP &kp, const Bufs &b) {
     const int nzf = kp.z1 - kp.z0;
     const dim3 grid(ntx * nty, (nzf + cz - 1) / cz);
     switch (prec) {
-        case LBFE_FP64: k_chain<LBFE_FP64><<<grid, kBlock, 0, s>>>(kp, b.rho, b.j, b.mu, b.F, b.Q, cz); break;
-        case LBFE_FP32: k_chain<LBFE_FP32><<<grid, kBlock, 0, s>>>(kp, b.rho, b.j, b.mu, b.F, b.Q, cz); break;
-        case LBFE_FP16_DEV: k_chain<LBFE_FP16_DEV><<<grid, kBlock, 0, s>>>(kp, b.rho, b.j, b.mu, b.F, b.Q, cz); break;
-        default: k_chain<LBFE_FP16_DEV_F0FP32><<<grid, kBlock, 0, s>>>(kp, b.rho, b.j, b.mu, b.F, b.Q, cz); break;
+        case LBFE_FP64: k_chain<LBFE_FP64><<<grid, CB, 0, s>>>(kp, b.rho, b.mu0, b.j, b.mu, b.F, b.Q, cz); break;
+        case LBFE_FP32: k_chain<LBFE_FP32><<<grid, CB, 0, s>>>(kp, b.rho, b.mu0, b.j, b.mu, b.F, b.Q, cz); break;
+        case LBFE_FP16_DEV: k_chain<LBFE_FP16_DEV><<<grid, CB, 0, s>>>(kp, b.rho, b.mu0, b.j, b.mu, b.F, b.Q, cz); break;
+        default: k_chain<LBFE_FP16_DEV_F0FP32><<<grid, CB, 0, s>>>(kp, b.rho, b.mu0, b.j, b.mu, b.F, b.Q, cz); break;
     }
     return hipGetLastError();
 }

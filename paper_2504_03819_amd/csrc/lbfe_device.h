@@ -168,30 +168,8 @@ __device__ inline void moments(const real (&f)[27], double &rho, real &jx, real 
 
 // Bulk chemical potential of the vdW fluid, Eq. (32) without the kappa term.
 __device__ inline double mu_bulk(const KP &kp, double r) {
-    const double d = 1.0 - kp.b * r;
-    return kp.RT * (log(r / d) + 1.0 / d) - 2.0 * kp.a * r;
-}
-
-// Q_aa = -3 d_a phi_a (Eq. (27)) with the isotropic gradient
-// d_a g = 3 sum_i w_i c_ia g(x + c_i); for the a-component only the 18
-// neighbours with c_a != 0 contribute: d_x g = 1/2 sum_{cy,cz} w(cy) w(cz)
-// [g(x+1,..) - g(x-1,..)].
-template <class real>
-__device__ inline void q_terms(const KP &kp, const Nb &nb, const real *phi, real &q200, real &q020, real &q002) {
-    const real *px = phi, *py = phi + kp.N, *pz = phi + 2 * (size_t)kp.N;
-    real sx = 0, sy = 0, sz = 0;
-#pragma unroll
-    for (int a = -1; a <= 1; ++a)
-#pragma unroll
-        for (int b = -1; b <= 1; ++b) {
-            const real w = (real)(w1(a) * w1(b));
-            sx += w * (px[nb.at(1, a, b)] - px[nb.at(-1, a, b)]);
-            sy += w * (py[nb.at(a, 1, b)] - py[nb.at(a, -1, b)]);
-            sz += w * (pz[nb.at(a, b, 1)] - pz[nb.at(a, b, -1)]);
-        }
-    q200 = (real)(-1.5) * sx;
-    q020 = (real)(-1.5) * sy;
-    q002 = (real)(-1.5) * sz;
+    const double id = 1.0 / (1.0 - kp.b * r);
+    return kp.RT * (log(r * id) + id) - 2.0 * kp.a * r;
 }
 
 // ---------------------------------------------------------------------------

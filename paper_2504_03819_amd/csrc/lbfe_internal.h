@@ -35,6 +35,7 @@ struct Bufs {
     double *rho;         // [N] density (solid planes: Eqs. (37)-(38))
     void *j;             // [3][N] sum_i f_i c_i, compute precision
     double *mu;          // [N] chemical potential (solid: Eq. (36))
+    double *mu0;         // [N] bulk part mu0(rho) of mu at fluid nodes
     void *F;             // [3][N] force, compute precision
     void *Q;             // [3][N] Q200, Q020, Q002 of Eq. (27), compute precision, 0 at solid
     int *flag;           // divergence / domain flag

@@ -2,7 +2,8 @@
 // (arXiv:2504.03819, Sec. II B and Sec. III C) for gfx950.
 //
 // One time step t -> t+1 on the post-streaming state f(t) is four launches:
-//   k_moments   rho (double) and j = sum f c of every fluid node     Eq. (11)
+//   k_moments   rho (double), j = sum f c and the bulk chemical
+//               potential mu0(rho) of every fluid node      Eqs. (11), (32)
 //   k_wall_rho  density of the solid nodes (walls only)         Eqs. (37)-(38)
 //   k_chain     mu, mu at walls, F, u, phi and Q with LDS-staged
 //               stencils (lbfe_chain.hip)     Eqs. (12), (27), (32), (36)
@@ -28,7 +29,8 @@ __global__ void k_fill(uint4 *p, size_t n16) {
 
 // --------------------------------------------------------------------------
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_moments(KP kp, const void *fq, double *rho, void *jq, int *flag) {
+__global__ __launch_bounds__(kBlock) void k_moments(KP kp, const void *fq, double *rho, void *jq, double *mu0,
+                                                    int *flag) {
     using real = real_t<P>;
     const unsigned idx = tile_id(kp) * kBlock + threadIdx.x;
     if (idx >= kp.nfluid) return;
@@ -42,6 +44,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(KP kp, const void *fq, doubl
     real jx, jy, jz;
     moments(v, r, jx, jy, jz);
     rho[n] = r;
+    mu0[n] = mu_bulk(kp, r);
     real *j = (real *)jq;
     j[n] = jx;
     j[kp.N + n] = jy;
@@ -132,11 +135,11 @@ __global__ __launch_bounds__(kBlock) void k_collide(KP kp, const void *fin_q, vo
     moments(f, rd, jx, jy, jz);
     const real *F = (const real *)Fq;
     const real Fx = F[n], Fy = F[kp.N + n], Fz = F[2 * (size_t)kp.N + n];
-    const real rho = (real)rd;
-    const real ux = (jx + (real)0.5 * Fx) / rho;
-    const real uy = (jy + (real)0.5 * Fy) / rho;
-    const real uz = (jz + (real)0.5 * Fz) / rho;
-    const real pm = (real)((1.0 + mu[n]) / 3.0);
+    const real rho = (real)rd, irho = (real)1 / rho;
+    const real ux = (jx + (real)0.5 * Fx) * irho;
+    const real uy = (jy + (real)0.5 * Fy) * irho;
+    const real uz = (jz + (real)0.5 * Fz) * irho;
+    const real pm = (real)((1.0 + mu[n]) * (1.0 / 3.0));
     const real *Qa = (const real *)Qq;
     const real q200 = Qa[n], q020 = Qa[kp.N + n], q002 = Qa[2 * (size_t)kp.N + n];
     real q220 = 0, q202 = 0, q022 = 0;
@@ -149,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_collide(KP kp, const void *fin_q, vo
     Rates<real> R;
 #pragma unroll
     for (int k = 0; k < 11; ++k) R.w[k] = (real)kp.om[k];
-    R.w[1] = (real)1 / (rho * (real)kp.nu / pm + (real)0.5);
+    R.w[1] = pm / (rho * (real)kp.nu + (real)0.5 * pm);  // 1 / (rho nu / p_m + 1/2)
 
     cm_forward(f, ux, uy, uz);
     collide(f, R, Fx, Fy, Fz, pm, q200, q020, q002, q220, q202, q022);
@@ -335,7 +338,7 @@ hipError_t aux_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur, hipEven
         if (ev) (void)hipEventRecord(ev[k], s);
     };
     mark(0);
-    k_moments<P><<<gf, kBlock, 0, s>>>(kp, b.f[cur], b.rho, b.j, b.flag);
+    k_moments<P><<<gf, kBlock, 0, s>>>(kp, b.f[cur], b.rho, b.j, b.mu0, b.flag);
     mark(1);
     if (kp.walls) k_wall_rho<<<gw, kBlock, 0, s>>>(kp, b.rho);
     mark(2);
