@@ -134,14 +134,22 @@ int lbfe_init_density(lbfe_ctx *ctx, const double *rho0_dev, const double *u0_de
  * Eq. (12), Q corrections Eqs. (27)-(28), central-moment collision
  * Eqs. (21)-(26), inverse transform and streaming Eq. (10) with halfway
  * bounce-back.  Checks the divergence flag every check_every steps and at
- * the end (a synchronisation): E_DIVERGED, with the step in lbfe_last_error. */
+ * the end (a synchronisation): E_DIVERGED, with the step in lbfe_last_error.
+ * Each step is the stencil chain plus one fused kernel that collides,
+ * streams and forms the next step's density and momentum; the environment
+ * variable LBFE_UNFUSED=1 at lbfe_create selects the unfused reference path
+ * (separate moments and collide-stream passes), which gives bitwise
+ * identical states. */
 int lbfe_step(lbfe_ctx *ctx, int64_t nsteps);
 
 /* Timing variant of lbfe_step for benchmarks: the same launches, with HIP
- * events recorded on the context's stream around every kernel;
- * kernel_ms[k] receives the summed milliseconds of kernel class k over the
- * nsteps steps: 0 moments, 1 wall density, 2 stencil chain (mu, force, Q),
- * 3 collide-stream.  Synchronises after every step (host array). */
+ * events recorded on the context's stream around every kernel class;
+ * kernel_ms[k] receives the summed milliseconds of class k over the nsteps
+ * steps: 0 moments pass (with the wall density after it; on the fused path
+ * only after the state was set from outside), 1 stencil chain (mu, force,
+ * Q), 2 collide-stream (fused path: with the next step's moments), 3 wall
+ * density after the step (fused path, walls only).  Synchronises after
+ * every step (host array). */
 int lbfe_step_timed(lbfe_ctx *ctx, int64_t nsteps, double kernel_ms[4]);
 
 /* Number of steps taken since lbfe_init_density / lbfe_set_state. */

@@ -25,6 +25,8 @@ struct lbfe_ctx {
     int lcur = 0;  // index of the current adjoint lattice
     int64_t step = 0;
     bool bound = false, initialised = false, adj_seeded = false;
+    bool fused = true;    // fused collide-stream-moments step (LBFE_UNFUSED=1: reference path)
+    bool aux_ok = false;  // rho, j, mu0 hold the moments of f[cur]
     std::string err;
 };
 
@@ -265,6 +267,10 @@ int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out) {
     // streaming kernels, so off by default (LBFE_XCD_REMAP=1 enables it).
     const char *remap = std::getenv("LBFE_XCD_REMAP");
     k.xcd_remap = (remap && remap[0] == '1') ? 1 : 0;
+    // LBFE_UNFUSED=1 selects the unfused reference step (separate moments
+    // and collide-stream passes); both paths give bitwise identical states.
+    const char *unf = std::getenv("LBFE_UNFUSED");
+    c->fused = !(unf && unf[0] == '1');
     *out = c;
     return LBFE_OK;
 }
@@ -300,6 +306,7 @@ int lbfe_bind_workspace(lbfe_ctx *c, void *ws, size_t bytes) {
     if (e != hipSuccess) return hip_fail(c, e, "workspace clear");
     c->bound = true;
     c->initialised = false;
+    c->aux_ok = false;
     c->adj_seeded = false;
     c->cur = 0;
     c->step = 0;
@@ -323,6 +330,7 @@ int lbfe_init_density(lbfe_ctx *c, const double *rho0, const double *u0) {
     if ((r = read_flag(c, flag))) return r;
     if (flag) return fail(c, LBFE_E_INVAL, "rho0 not finite or outside 0 < rho < 1/b at a fluid node");
     c->cur = 0;
+    c->aux_ok = false;
     e = launch_init(c->stream, c->p.precision, c->kp, c->b, c->cur, rho0, u0);
     if (e != hipSuccess) return hip_fail(c, e, "init");
     c->step = 0;
@@ -335,10 +343,11 @@ int lbfe_step(lbfe_ctx *c, int64_t nsteps) {
     if (r) return r;
     if (nsteps < 0) return fail(c, LBFE_E_INVAL, "nsteps < 0");
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = launch_step(c->stream, c->p.precision, c->kp, c->b, c->cur);
+        hipError_t e = launch_step(c->stream, c->p.precision, c->kp, c->b, c->cur, c->fused, !c->aux_ok, nullptr);
         if (e != hipSuccess) return hip_fail(c, e, "step");
         c->cur ^= 1;
         c->step++;
+        c->aux_ok = c->fused;
         if ((s + 1) % c->p.check_every == 0 || s + 1 == nsteps) {
             int flag = 0;
             if ((r = read_flag(c, flag))) return r;
@@ -366,7 +375,7 @@ int lbfe_step_timed(lbfe_ctx *c, int64_t nsteps, double kernel_ms[4]) {
     for (int k = 0; k < 4; ++k) kernel_ms[k] = 0.0;
     int rc = LBFE_OK;
     for (int64_t s = 0; s < nsteps && rc == LBFE_OK; ++s) {
-        hipError_t e = launch_step_timed(c->stream, c->p.precision, c->kp, c->b, c->cur, ev);
+        hipError_t e = launch_step(c->stream, c->p.precision, c->kp, c->b, c->cur, c->fused, !c->aux_ok, ev);
         if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
         if (e != hipSuccess) {
             rc = hip_fail(c, e, "step_timed");
@@ -379,6 +388,7 @@ int lbfe_step_timed(lbfe_ctx *c, int64_t nsteps, double kernel_ms[4]) {
         }
         c->cur ^= 1;
         c->step++;
+        c->aux_ok = c->fused;
     }
     for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
     if (rc == LBFE_OK) {
@@ -442,6 +452,7 @@ int lbfe_set_state(lbfe_ctx *c, const void *src, int64_t step) {
     hipError_t e = hipMemcpyAsync(c->b.f[c->cur], src, pop_bytes(c->p.precision, c->kp.N), hipMemcpyDeviceToDevice,
                                   c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "set_state");
+    c->aux_ok = false;
     c->step = step;
     c->initialised = true;
     return LBFE_OK;
@@ -462,6 +473,7 @@ int lbfe_set_populations(lbfe_ctx *c, const double *f) {
     if (!f) return fail(c, LBFE_E_INVAL, "null source");
     hipError_t e = launch_set_pop(c->stream, c->p.precision, c->kp, c->b.f[c->cur], f);
     if (e != hipSuccess) return hip_fail(c, e, "set_populations");
+    c->aux_ok = false;
     c->initialised = true;
     return LBFE_OK;
 }
@@ -519,6 +531,7 @@ int lbfe_adjoint_step(lbfe_ctx *c, const void *ft) {
     if (!c->p.adjoint) return fail(c, LBFE_E_STATE, "created without params.adjoint = 1");
     if (!c->adj_seeded) return fail(c, LBFE_E_STATE, "adjoint not seeded");
     if (!ft) return fail(c, LBFE_E_INVAL, "null state");
+    c->aux_ok = false;  // the recomputation below overwrites rho, j, mu0
     hipError_t e = launch_adj_step(c->stream, c->p.precision, c->kp, c->b, c->lcur, ft);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
     c->lcur ^= 1;
@@ -531,6 +544,7 @@ int lbfe_adjoint_init_density(lbfe_ctx *c, const double *rho0, const double *u0,
     if (!c->p.adjoint) return fail(c, LBFE_E_STATE, "created without params.adjoint = 1");
     if (!c->adj_seeded) return fail(c, LBFE_E_STATE, "adjoint not seeded");
     if (!rho0 || !out) return fail(c, LBFE_E_INVAL, "null rho0 or output");
+    c->aux_ok = false;
     hipError_t e = launch_adj_init(c->stream, c->p.precision, c->kp, c->b, c->lcur, rho0, u0, out);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_init_density");
     return LBFE_OK;

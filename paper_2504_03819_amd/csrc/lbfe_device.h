@@ -43,6 +43,7 @@ template <> struct Pops<LBFE_FP64> {
     __device__ size_t off(int i, unsigned row, unsigned x) const { return ((size_t)row * 27 + i) * nx + x; }
     __device__ double ld(int i, unsigned row, unsigned x) const { return p[off(i, row, x)]; }
     __device__ void st(int i, unsigned row, unsigned x, double v) const { p[off(i, row, x)] = v; }
+    __device__ static double quant(int, double v) { return v; }  // value a store then load returns
 };
 
 template <> struct Pops<LBFE_FP32> {
@@ -52,6 +53,7 @@ template <> struct Pops<LBFE_FP32> {
     __device__ size_t off(int i, unsigned row, unsigned x) const { return ((size_t)row * 27 + i) * nx + x; }
     __device__ float ld(int i, unsigned row, unsigned x) const { return p[off(i, row, x)]; }
     __device__ void st(int i, unsigned row, unsigned x, float v) const { p[off(i, row, x)] = v; }
+    __device__ static float quant(int, float v) { return v; }
 };
 
 // Half-precision deviation from the rest-state weight, scaled by the weight:
@@ -64,7 +66,12 @@ __device__ inline float dec16(int i, __half h) {
 }
 __device__ inline __half enc16(int i, float f) {
     const float iw = (float)(1.0 / wi(i));
-    return __float2half_rn(fmaf(f, iw, -1.0f));
+    float t = fmaf(f, iw, -1.0f);
+    // t is rounded to float before the conversion (no fused
+    // multiply-add-convert instruction), so every kernel encodes a value to
+    // the same half
+    __asm__ volatile("" : "+v"(t));
+    return __float2half_rn(t);
 }
 
 template <> struct Pops<LBFE_FP16_DEV> {
@@ -74,6 +81,7 @@ template <> struct Pops<LBFE_FP16_DEV> {
     __device__ size_t off(int i, unsigned row, unsigned x) const { return ((size_t)row * 27 + i) * nx + x; }
     __device__ float ld(int i, unsigned row, unsigned x) const { return dec16(i, p[off(i, row, x)]); }
     __device__ void st(int i, unsigned row, unsigned x, float v) const { p[off(i, row, x)] = enc16(i, v); }
+    __device__ static float quant(int i, float v) { return dec16(i, enc16(i, v)); }
 };
 
 // Rest population in float ([z][y][x] plane after the half rows), the 26
@@ -96,6 +104,7 @@ template <> struct Pops<LBFE_FP16_DEV_F0FP32> {
         else
             p[off(i, row, x)] = enc16(i, v);
     }
+    __device__ static float quant(int i, float v) { return i == kRest ? v : dec16(i, enc16(i, v)); }
 };
 
 // ---------------------------------------------------------------------------
@@ -142,28 +151,49 @@ __device__ inline void decompose(const KP &kp, unsigned n, int &x, int &y, int &
 }
 
 // ---------------------------------------------------------------------------
-// Macroscopic moments, Eq. (11): rho = sum f (accumulated in double),
-// j = sum f c.
+// Macroscopic moments, Eq. (11): rho = sum f, j = sum f c, of the 27
+// populations arriving at a node, summed in one fixed order in double:
+// per z-layer cz and row cy the x-partials
+//   R = (f(0,cy,cz) + f(+1,cy,cz)) + f(-1,cy,cz),  X = f(+1,cy,cz) - f(-1,cy,cz),
+// per layer L = (R(0) + R(+1)) + R(-1), JX = (X(0) + X(+1)) + X(-1),
+// JY = R(+1) - R(-1), and over the layers
+//   rho = (L(+1) + L(0)) + L(-1),  jx, jy likewise,  jz = L(+1) - L(-1).
+// The fused step kernel forms the same partial sums from values exchanged
+// between neighbouring nodes, so the density and momentum it writes are bit
+// for bit those of this function applied to the stored populations.
 // ---------------------------------------------------------------------------
+__host__ __device__ constexpr int dir(int cx, int cy, int cz) { return 9 * (cx + 1) + 3 * (cy + 1) + (cz + 1); }
+
+struct Layer {
+    double L, JX, JY;
+};
+
+// x-partials of row (cy, cz) from the centre value and the values arriving
+// from x-1 (fp, direction +1) and x+1 (fm, direction -1)
+__device__ inline void xpartial(double f0, double fp, double fm, double &R, double &X) {
+    R = (f0 + fp) + fm;
+    X = fp - fm;
+}
+__device__ inline Layer layer_of(const double (&R)[3], const double (&X)[3]) {  // index cy + 1
+    return Layer{(R[1] + R[2]) + R[0], (X[1] + X[2]) + X[0], R[2] - R[0]};
+}
+
+template <class real> __device__ inline Layer layer_sum(const real (&f)[27], int cz) {
+    double R[3], X[3];
+#pragma unroll
+    for (int cy = -1; cy <= 1; ++cy)
+        xpartial((double)f[dir(0, cy, cz)], (double)f[dir(1, cy, cz)], (double)f[dir(-1, cy, cz)], R[cy + 1],
+                 X[cy + 1]);
+    return layer_of(R, X);
+}
+
 template <class real>
 __device__ inline void moments(const real (&f)[27], double &rho, real &jx, real &jy, real &jz) {
-    double r = 0.0;
-#pragma unroll
-    for (int i = 0; i < 27; ++i) r += (double)f[i];
-    rho = r;
-    real px = 0, mx = 0, py = 0, my = 0, pz = 0, mz = 0;
-#pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        if (cxi(i) > 0) px += f[i];
-        if (cxi(i) < 0) mx += f[i];
-        if (cyi(i) > 0) py += f[i];
-        if (cyi(i) < 0) my += f[i];
-        if (czi(i) > 0) pz += f[i];
-        if (czi(i) < 0) mz += f[i];
-    }
-    jx = px - mx;
-    jy = py - my;
-    jz = pz - mz;
+    const Layer P = layer_sum(f, 1), Z = layer_sum(f, 0), M = layer_sum(f, -1);
+    rho = (P.L + Z.L) + M.L;
+    jx = (real)((P.JX + Z.JX) + M.JX);
+    jy = (real)((P.JY + Z.JY) + M.JY);
+    jz = (real)(P.L - M.L);
 }
 
 // Bulk chemical potential of the vdW fluid, Eq. (32) without the kappa term.
@@ -294,6 +324,39 @@ __device__ inline void collide(real (&k)[27], const Rates<real> &R, real Fx, rea
     }
     // sixth order, Eq. (26)
     k[K(2, 2, 2)] = (one - w[10]) * k[K(2, 2, 2)] + w[10] * pm * ninth;
+}
+
+// ---------------------------------------------------------------------------
+// Collision of one fluid node: moments, u = (j + F/2)/rho, the local
+// omega_1 = 1/(rho nu/p_m + 1/2), CM transform, Eqs. (21)-(26), inverse
+// transform.  f: the arriving populations in, post-collision out.
+// ---------------------------------------------------------------------------
+template <class real>
+__device__ inline void collide_node(const KP &kp, real (&f)[27], double mu, real Fx, real Fy, real Fz, real q200,
+                                    real q020, real q002) {
+    double rd;
+    real jx, jy, jz;
+    moments(f, rd, jx, jy, jz);
+    const real rho = (real)rd, irho = (real)1 / rho;
+    const real ux = (jx + (real)0.5 * Fx) * irho;
+    const real uy = (jy + (real)0.5 * Fy) * irho;
+    const real uz = (jz + (real)0.5 * Fz) * irho;
+    const real pm = (real)((1.0 + mu) * (1.0 / 3.0));
+    real q220 = 0, q202 = 0, q022 = 0;
+    if (kp.corr4) {  // Eq. (28)
+        const real third = (real)(1.0 / 3.0);
+        q220 = (q200 + q020) * third;
+        q202 = (q200 + q002) * third;
+        q022 = (q020 + q002) * third;
+    }
+    Rates<real> R;
+#pragma unroll
+    for (int k = 0; k < 11; ++k) R.w[k] = (real)kp.om[k];
+    R.w[1] = pm / (rho * (real)kp.nu + (real)0.5 * pm);  // 1 / (rho nu / p_m + 1/2)
+
+    cm_forward(f, ux, uy, uz);
+    collide(f, R, Fx, Fy, Fz, pm, q200, q020, q002, q220, q202, q022);
+    cm_inverse(f, ux, uy, uz);
 }
 
 }  // namespace lbfe

@@ -52,8 +52,13 @@ hipError_t launch_fill(hipStream_t s, void *p, size_t bytes);
 hipError_t launch_init(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, const double *rho0,
                        const double *u0);
 hipError_t launch_aux(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur);
-hipError_t launch_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur);
-hipError_t launch_step_timed(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, hipEvent_t *ev5);
+// One step f[cur] -> f[1 - cur].  fused: chain + fused collide-stream-moments
+// (+ wall density), with a moments pass first if `refresh`; otherwise the
+// unfused moments, chain, collide-stream.  ev5: optional timing events.
+hipError_t launch_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, bool fused, bool refresh,
+                       hipEvent_t *ev5);
+// collide + push-stream + rho, j, mu0 of the streamed state (lbfe_fused.hip)
+hipError_t launch_fused(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur);
 // mu, F and Q of the current rho, j (lbfe_chain.hip)
 hipError_t launch_chain(hipStream_t s, int prec, const KP &kp, const Bufs &b);
 hipError_t launch_export(hipStream_t s, int prec, const KP &kp, const Bufs &b, int which, double *out);

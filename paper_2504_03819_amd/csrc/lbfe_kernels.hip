@@ -1,14 +1,17 @@
 // Forward kernels of the D3Q27 chemical-potential free-energy LB step
 // (arXiv:2504.03819, Sec. II B and Sec. III C) for gfx950.
 //
-// One time step t -> t+1 on the post-streaming state f(t) is four launches:
-//   k_moments   rho (double), j = sum f c and the bulk chemical
-//               potential mu0(rho) of every fluid node      Eqs. (11), (32)
+// One time step t -> t+1 on the post-streaming state f(t):
+//   k_chain     mu, mu at walls, F, u, phi and Q from rho, j, mu0 with
+//               LDS-staged stencils (lbfe_chain.hip)
+//                                              Eqs. (12), (27), (32), (36)
+//   k_fused     CM transform, collision, inverse, push-stream with halfway
+//               bounce-back, and rho, j, mu0 of f(t+1) (lbfe_fused.hip)
+//                                  Eqs. (10), (11), (21)-(26), (28), (32)
 //   k_wall_rho  density of the solid nodes (walls only)         Eqs. (37)-(38)
-//   k_chain     mu, mu at walls, F, u, phi and Q with LDS-staged
-//               stencils (lbfe_chain.hip)     Eqs. (12), (27), (32), (36)
-//   k_collide   CM transform, collision, inverse, push-stream with halfway
-//               bounce-back                       Eqs. (10), (21)-(26), (28)  Populations are row-blocked
+// k_moments forms rho (double), j = sum f c and mu0(rho) from stored
+// populations when they were set from outside (Eqs. (11), (32)); k_collide
+// is the collide-stream alone, for the unfused reference path.  Populations are row-blocked
 // (each x-row holds its 27 populations as 27 contiguous runs); one thread per
 // node, x fastest, so every population load and store of a wave64 is one
 // contiguous 64-element run.
@@ -130,33 +133,9 @@ __global__ __launch_bounds__(kBlock) void k_collide(KP kp, const void *fin_q, vo
     real f[27];
 #pragma unroll
     for (int i = 0; i < 27; ++i) f[i] = fin.ld(i, row, (unsigned)x);
-    double rd;
-    real jx, jy, jz;
-    moments(f, rd, jx, jy, jz);
-    const real *F = (const real *)Fq;
-    const real Fx = F[n], Fy = F[kp.N + n], Fz = F[2 * (size_t)kp.N + n];
-    const real rho = (real)rd, irho = (real)1 / rho;
-    const real ux = (jx + (real)0.5 * Fx) * irho;
-    const real uy = (jy + (real)0.5 * Fy) * irho;
-    const real uz = (jz + (real)0.5 * Fz) * irho;
-    const real pm = (real)((1.0 + mu[n]) * (1.0 / 3.0));
-    const real *Qa = (const real *)Qq;
-    const real q200 = Qa[n], q020 = Qa[kp.N + n], q002 = Qa[2 * (size_t)kp.N + n];
-    real q220 = 0, q202 = 0, q022 = 0;
-    if (kp.corr4) {  // Eq. (28)
-        const real third = (real)(1.0 / 3.0);
-        q220 = (q200 + q020) * third;
-        q202 = (q200 + q002) * third;
-        q022 = (q020 + q002) * third;
-    }
-    Rates<real> R;
-#pragma unroll
-    for (int k = 0; k < 11; ++k) R.w[k] = (real)kp.om[k];
-    R.w[1] = pm / (rho * (real)kp.nu + (real)0.5 * pm);  // 1 / (rho nu / p_m + 1/2)
-
-    cm_forward(f, ux, uy, uz);
-    collide(f, R, Fx, Fy, Fz, pm, q200, q020, q002, q220, q202, q022);
-    cm_inverse(f, ux, uy, uz);
+    const real *F = (const real *)Fq, *Qa = (const real *)Qq;
+    collide_node(kp, f, mu[n], F[n], F[kp.N + n], F[2 * (size_t)kp.N + n], Qa[n], Qa[kp.N + n],
+                 Qa[2 * (size_t)kp.N + n]);
 
     const bool wall_lo = kp.walls && z == 1;
     const bool wall_hi = kp.walls && z == kp.nz - 2;
@@ -328,32 +307,46 @@ __global__ __launch_bounds__(kBlock) void k_set_pop(KP kp, void *fq, const doubl
 }
 
 // --------------------------------------------------------------------------
-// One step's launches.  With `ev` non-null, HIP events are recorded on the
-// stream before the first kernel and after each of the four kernel classes
-// (moments, wall density, chain, collide-stream).
+// One step's launches.  With `ev` non-null, HIP events ev[0..4] bracket the
+// four kernel classes in the order: moments (with the wall density that
+// follows them), chain, collide-stream, wall density after the step.
 template <int P>
-hipError_t aux_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur, hipEvent_t *ev = nullptr) {
+hipError_t aux_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur) {
+    const unsigned gf = nblocks(kp.nfluid), gw = nblocks(2 * (size_t)kp.plane);
+    k_moments<P><<<gf, kBlock, 0, s>>>(kp, b.f[cur], b.rho, b.j, b.mu0, b.flag);
+    if (kp.walls) k_wall_rho<<<gw, kBlock, 0, s>>>(kp, b.rho);
+    hipError_t e = launch_chain(s, P, kp, b);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+// Fused path: rho, j, mu0 of f[cur] are current unless `refresh`; the fused
+// kernel leaves them current for f[1 - cur].
+template <int P>
+hipError_t step_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur, bool fused, bool refresh,
+                     hipEvent_t *ev) {
     const unsigned gf = nblocks(kp.nfluid), gw = nblocks(2 * (size_t)kp.plane);
     auto mark = [&](int k) {
         if (ev) (void)hipEventRecord(ev[k], s);
     };
     mark(0);
-    k_moments<P><<<gf, kBlock, 0, s>>>(kp, b.f[cur], b.rho, b.j, b.mu0, b.flag);
+    if (refresh || !fused) {
+        k_moments<P><<<gf, kBlock, 0, s>>>(kp, b.f[cur], b.rho, b.j, b.mu0, b.flag);
+        if (kp.walls) k_wall_rho<<<gw, kBlock, 0, s>>>(kp, b.rho);
+    }
     mark(1);
-    if (kp.walls) k_wall_rho<<<gw, kBlock, 0, s>>>(kp, b.rho);
-    mark(2);
     hipError_t e = launch_chain(s, P, kp, b);
+    if (e != hipSuccess) return e;
+    mark(2);
+    if (fused) {
+        e = launch_fused(s, P, kp, b, cur);
+        if (e != hipSuccess) return e;
+    } else {
+        k_collide<P><<<nblocks(kp.nfluid), kBlock, 0, s>>>(kp, b.f[cur], b.f[1 - cur], b.mu, b.F, b.Q);
+    }
     mark(3);
-    if (e != hipSuccess) return e;
-    return hipGetLastError();
-}
-
-template <int P>
-hipError_t step_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur, hipEvent_t *ev = nullptr) {
-    hipError_t e = aux_impl<P>(s, kp, b, cur, ev);
-    if (e != hipSuccess) return e;
-    k_collide<P><<<nblocks(kp.nfluid), kBlock, 0, s>>>(kp, b.f[cur], b.f[1 - cur], b.mu, b.F, b.Q);
-    if (ev) (void)hipEventRecord(ev[4], s);
+    if (fused && kp.walls) k_wall_rho<<<gw, kBlock, 0, s>>>(kp, b.rho);
+    mark(4);
     return hipGetLastError();
 }
 
@@ -397,12 +390,10 @@ hipError_t launch_aux(hipStream_t s, int prec, const KP &kp, const Bufs &b, int 
     return dispatch(prec, [&](auto pc) { return aux_impl<decltype(pc)::value>(s, kp, b, cur); });
 }
 
-hipError_t launch_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur) {
-    return dispatch(prec, [&](auto pc) { return step_impl<decltype(pc)::value>(s, kp, b, cur); });
-}
-
-hipError_t launch_step_timed(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, hipEvent_t *ev) {
-    return dispatch(prec, [&](auto pc) { return step_impl<decltype(pc)::value>(s, kp, b, cur, ev); });
+hipError_t launch_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, bool fused, bool refresh,
+                       hipEvent_t *ev5) {
+    return dispatch(prec,
+                    [&](auto pc) { return step_impl<decltype(pc)::value>(s, kp, b, cur, fused, refresh, ev5); });
 }
 
 hipError_t launch_export(hipStream_t s, int prec, const KP &kp, const Bufs &b, int which, double *out) {

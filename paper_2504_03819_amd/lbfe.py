@@ -186,7 +186,7 @@ class Simulation:
     def step(self, n=1):
         self._check(lib().lbfe_step(self._ctx, c_int64(int(n))))
 
-    KERNELS = ("moments", "wall_rho", "chain", "collide_stream")
+    KERNELS = ("moments", "chain", "collide_stream", "wall_rho")
 
     def step_timed(self, n):
         """Run n steps with HIP events around each kernel; returns the summed
