@@ -135,11 +135,10 @@ int lbfe_init_density(lbfe_ctx *ctx, const double *rho0_dev, const double *u0_de
  * Eqs. (21)-(26), inverse transform and streaming Eq. (10) with halfway
  * bounce-back.  Checks the divergence flag every check_every steps and at
  * the end (a synchronisation): E_DIVERGED, with the step in lbfe_last_error.
- * Each step is the stencil chain plus one fused kernel that collides,
- * streams and forms the next step's density and momentum; the environment
- * variable LBFE_UNFUSED=1 at lbfe_create selects the unfused reference path
- * (separate moments and collide-stream passes), which gives bitwise
- * identical states. */
+ * Each step is a moments pass, the stencil chain and a collide-stream
+ * pass; the environment variable LBFE_FUSED=1 at lbfe_create selects a
+ * path whose collide-stream kernel also forms the next step's density and
+ * momentum (no moments pass), which gives bitwise identical states. */
 int lbfe_step(lbfe_ctx *ctx, int64_t nsteps);
 
 /* Timing variant of lbfe_step for benchmarks: the same launches, with HIP

@@ -25,7 +25,7 @@ struct lbfe_ctx {
     int lcur = 0;  // index of the current adjoint lattice
     int64_t step = 0;
     bool bound = false, initialised = false, adj_seeded = false;
-    bool fused = true;    // fused collide-stream-moments step (LBFE_UNFUSED=1: reference path)
+    bool fused = false;   // fused collide-stream-moments step (LBFE_FUSED=1)
     bool aux_ok = false;  // rho, j, mu0 hold the moments of f[cur]
     std::string err;
 };
@@ -267,10 +267,15 @@ int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out) {
     // streaming kernels, so off by default (LBFE_XCD_REMAP=1 enables it).
     const char *remap = std::getenv("LBFE_XCD_REMAP");
     k.xcd_remap = (remap && remap[0] == '1') ? 1 : 0;
-    // LBFE_UNFUSED=1 selects the unfused reference step (separate moments
-    // and collide-stream passes); both paths give bitwise identical states.
-    const char *unf = std::getenv("LBFE_UNFUSED");
-    c->fused = !(unf && unf[0] == '1');
+    // Step path: separate moments and collide-stream passes by default;
+    // LBFE_FUSED=1 selects the fused collide-stream-moments kernel.  Both
+    // give bitwise identical states.  The fused kernel removes the moments
+    // pass's population read but re-reads a one-node ring of populations per
+    // tile and needs twice the vector instructions per node at two waves per
+    // SIMD; measured on gfx950 it is on par in FP64 and slower in the FP32
+    // and FP16 forms.
+    const char *fu = std::getenv("LBFE_FUSED");
+    c->fused = fu && fu[0] == '1';
     *out = c;
     return LBFE_OK;
 }

@@ -26,12 +26,12 @@ CASES = [
 
 
 def _sim(unfused, **kw):
-    if unfused:
-        os.environ["LBFE_UNFUSED"] = "1"
+    if not unfused:
+        os.environ["LBFE_FUSED"] = "1"
     try:
         return make_sim(**kw)
     finally:
-        os.environ.pop("LBFE_UNFUSED", None)
+        os.environ.pop("LBFE_FUSED", None)
 
 
 def _raw(t):
@@ -76,7 +76,7 @@ def test_restart_from_state_is_bitwise_continuous(form):
     on exactly like the uninterrupted fused run."""
     T = eos.temperature(0.85)
     shape = (36, 33, 40)
-    sim = make_sim(nx=40, ny=33, nz=36, T=T, precision=form)
+    sim = _sim(False, nx=40, ny=33, nz=36, T=T, precision=form)
     sim.init_density(torch.tensor(droplet_rho(shape, T)))
     sim.step(4)
     s4 = sim.get_state().clone()
