@@ -323,107 +323,205 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     A[A_NUC * N + n] = nub;
 }
 
-// phi_bar = transpose of Q_a = -9 sum_i w_i c_ia phi_a(x + c_i), then back
-// through phi = (p_m - rho/3) u, u = (j + F/2)/rho, F = (1/3 - rho) G.
-template <int P> __global__ __launch_bounds__(kBlock) void k_adj_phi(KP kp, Bufs b) {
+// ---------------------------------------------------------------------------
+// z-marching tiles for the transposed stencils.  A workgroup owns a 32 x 8
+// column tile of one z-chunk.  The stencil inputs of four consecutive planes
+// (tile + one-node halo) sit in an LDS ring; plane k+2 is loaded into
+// registers while plane k is evaluated, so one barrier per plane suffices
+// (the slot written at plane k+1 was last read at plane k-2).  Plane indices
+// wrap periodically, as in the forward kernels; in a walled box the
+// wrapped planes are solid and the fields read there are zero or unused.
+// ---------------------------------------------------------------------------
+constexpr int ZTX = 32, ZTY = 8, ZWX = ZTX + 2, ZNR = ZWX * (ZTY + 2), ZCB = ZTX * ZTY;
+constexpr int ZM = (ZNR + ZCB - 1) / ZCB;  // halo-region points per thread
+
+__device__ inline int zwrap(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+template <int NF> struct ZRing {
+    double (*lds)[NF][ZNR];  // [4][NF][ZNR]
+    const double *src[NF];
+    int a, b, tid, nz;
+    bool own;       // the tile point is inside the grid
+    unsigned node;  // its in-plane index
+    unsigned plane;
+    unsigned off[ZM];
+    bool has[ZM];
+    double pre[NF][ZM];
+    unsigned zmask;  // fields zeroed on non-fluid planes (bit f)
+    const KP *kp;
+
+    __device__ void init(const KP &k, double (*l)[NF][ZNR], int x0, int y0) {
+        kp = &k;
+        lds = l;
+        tid = threadIdx.x;
+        a = tid % ZTX;
+        b = tid / ZTX;
+        nz = k.nz;
+        plane = k.plane;
+        own = x0 + a < k.nx && y0 + b < k.ny;
+        node = own ? (unsigned)(y0 + b) * k.nx + (x0 + a) : 0u;
+        zmask = 0;
+#pragma unroll
+        for (int m = 0; m < ZM; ++m) {
+            const int r = tid + m * ZCB;
+            has[m] = r < ZNR;
+            const int rr = has[m] ? r : 0;
+            off[m] = (unsigned)zwrap(y0 + rr / ZWX - 1, k.ny) * k.nx + zwrap(x0 + rr % ZWX - 1, k.nx);
+        }
+    }
+    __device__ void load(int p) {
+        const int zz = zwrap(p, nz);
+        const size_t base = (size_t)zz * plane;
+        const bool fl = zz >= kp->z0 && zz < kp->z1;
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int m = 0; m < ZM; ++m)
+                if (has[m]) pre[f][m] = ((zmask >> f) & 1) && !fl ? 0.0 : src[f][base + off[m]];
+    }
+    __device__ void commit(int p) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+#pragma unroll
+            for (int m = 0; m < ZM; ++m)
+                if (has[m]) lds[p & 3][f][tid + m * ZCB] = pre[f][m];
+    }
+    // field f at (x + dx, y + dy, plane p)
+    __device__ double at(int f, int p, int dx, int dy) const { return lds[p & 3][f][(b + 1 + dy) * ZWX + a + 1 + dx]; }
+    // planes [zs, ze) of the chunk, body(k) once per plane after the barrier
+    template <class Body> __device__ void march(int zs, int ze, Body body) {
+        load(zs - 1);
+        commit(zs - 1);
+        load(zs);
+        commit(zs);
+        load(zs + 1);
+        for (int k = zs; k < ze; ++k) {
+            commit(k + 1);
+            __syncthreads();
+            if (k + 1 < ze) load(k + 2);
+            body(k);
+        }
+    }
+};
+
+__device__ inline void ztile(const KP &kp, int cz, int zlo, int zhi, int &x0, int &y0, int &zs, int &ze) {
+    const int ntx = (kp.nx + ZTX - 1) / ZTX;
+    x0 = (int)(blockIdx.x % ntx) * ZTX;
+    y0 = (int)(blockIdx.x / ntx) * ZTY;
+    zs = zlo + (int)blockIdx.y * cz;
+    ze = min(zs + cz, zhi);
+}
+
+// phi_bar_a = transpose of Q_a = -9 sum_i w_i c_ia phi_a(x + c_i)
+// = 9 sum_i w_i c_ia Q_bar_a(x + c_i), then back through
+// phi = (p_m - rho/3) u, u = (j + F/2)/rho, F = (1/3 - rho) G, at fluid nodes.
+template <int P> __global__ __launch_bounds__(ZCB) void k_adj_phi(KP kp, Bufs b, int cz) {
     using real = real_t<P>;
-    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
-    if (idx >= kp.nfluid) return;
-    const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
-    int x, y, z;
-    decompose(kp, n, x, y, z);
-    const Nb nb(kp, x, y, z);
+    __shared__ double lds[4][4][ZNR];
+    int x0, y0, zs, ze;
+    ztile(kp, cz, kp.z0, kp.z1, x0, y0, zs, ze);
     const size_t N = kp.N;
     double *A = (double *)b.abuf;
-    const double *qbx = A + A_QB * N, *qby = A + (A_QB + 1) * N, *qbz = A + (A_QB + 2) * N;
-    double px = 0, py = 0, pz = 0;
-    // transposed stencil: +9 sum_i w_i c_ia Qbar_a(x + c_i)
-#pragma unroll
-    for (int a = -1; a <= 1; ++a)
-#pragma unroll
-        for (int c = -1; c <= 1; ++c) {
-            const double w = w1(a) * w1(c) / 6.0;
-            px += w * (qbx[nb.at(1, a, c)] - qbx[nb.at(-1, a, c)]);
-            py += w * (qby[nb.at(a, 1, c)] - qby[nb.at(a, -1, c)]);
-            pz += w * (qbz[nb.at(a, c, 1)] - qbz[nb.at(a, c, -1)]);
-        }
-    px *= 9.0;
-    py *= 9.0;
-    pz *= 9.0;
-    // forward quantities at x (same arithmetic as k_force)
-    const double r = b.rho[n], mu = b.mu[n];
+    ZRing<4> R;
+    R.init(kp, lds, x0, y0);
+    R.src[0] = A + A_QB * N;
+    R.src[1] = A + (A_QB + 1) * N;
+    R.src[2] = A + (A_QB + 2) * N;
+    R.src[3] = b.mu;
     const real *j = (const real *)b.j, *F = (const real *)b.F;
-    const real rr = (real)r;
-    const double Fx = (double)F[n], Fy = (double)F[N + n], Fz = (double)F[2 * N + n];
-    const double ux = (double)((j[n] + (real)0.5 * F[n]) / rr);
-    const double uy = (double)((j[N + n] + (real)0.5 * F[N + n]) / rr);
-    const double uz = (double)((j[2 * N + n] + (real)0.5 * F[2 * N + n]) / rr);
-    const double pm = (1.0 + mu) / 3.0;
-    const double c2 = pm - r / 3.0;
-    double pmb = A[A_PMB * N + n], rhob = A[A_RHOB * N + n];
-    const double pu = px * ux + py * uy + pz * uz;
-    pmb += pu;
-    rhob -= pu / 3.0;
-    const double utx = A[A_UB * N + n] + c2 * px;
-    const double uty = A[(A_UB + 1) * N + n] + c2 * py;
-    const double utz = A[(A_UB + 2) * N + n] + c2 * pz;
-    // u = (j + F/2)/rho
-    A[A_JB * N + n] = utx / r;
-    A[(A_JB + 1) * N + n] = uty / r;
-    A[(A_JB + 2) * N + n] = utz / r;
-    const double Fbx = A[A_FB * N + n] + 0.5 * utx / r;
-    const double Fby = A[(A_FB + 1) * N + n] + 0.5 * uty / r;
-    const double Fbz = A[(A_FB + 2) * N + n] + 0.5 * utz / r;
-    rhob -= (utx * ux + uty * uy + utz * uz) / r;
-    // F = (1/3 - rho) G, G recomputed as in k_force
-    double gx = 0.0, gy = 0.0, gz = 0.0;
+    R.march(zs, ze, [&](int k) {
+        if (!R.own) return;
+        double px = 0, py = 0, pz = 0;
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        if (i == kRest) continue;
-        const double m = wi(i) * b.mu[nb.at(cxi(i), cyi(i), czi(i))];
-        if (cxi(i)) gx += cxi(i) * m;
-        if (cyi(i)) gy += cyi(i) * m;
-        if (czi(i)) gz += czi(i) * m;
-    }
-    gx *= 3.0;
-    gy *= 3.0;
-    gz *= 3.0;
-    (void)Fx;
-    (void)Fy;
-    (void)Fz;
-    const double c1 = 1.0 / 3.0 - r;
-    A[A_GB * N + n] = c1 * Fbx;
-    A[(A_GB + 1) * N + n] = c1 * Fby;
-    A[(A_GB + 2) * N + n] = c1 * Fbz;
-    rhob -= Fbx * gx + Fby * gy + Fbz * gz;
-    A[A_RHOB * N + n] = rhob;
-    A[A_MUB * N + n] = pmb / 3.0;  // local part of mu_bar (p_m = (1 + mu)/3)
+        for (int a = -1; a <= 1; ++a)
+#pragma unroll
+            for (int c = -1; c <= 1; ++c) {
+                const double w = w1(a) * w1(c) / 6.0;
+                px += w * (R.at(0, k + c, 1, a) - R.at(0, k + c, -1, a));
+                py += w * (R.at(1, k + c, a, 1) - R.at(1, k + c, a, -1));
+                pz += w * (R.at(2, k + 1, a, c) - R.at(2, k - 1, a, c));
+            }
+        px *= 9.0;
+        py *= 9.0;
+        pz *= 9.0;
+        const size_t n = (size_t)k * kp.plane + R.node;
+        // forward quantities at x (same arithmetic as the chain kernel)
+        const double r = b.rho[n], mu = R.at(3, k, 0, 0);
+        const real rr = (real)r;
+        const double ux = (double)((j[n] + (real)0.5 * F[n]) / rr);
+        const double uy = (double)((j[N + n] + (real)0.5 * F[N + n]) / rr);
+        const double uz = (double)((j[2 * N + n] + (real)0.5 * F[2 * N + n]) / rr);
+        const double pm = (1.0 + mu) / 3.0;
+        const double c2 = pm - r / 3.0;
+        double pmb = A[A_PMB * N + n], rhob = A[A_RHOB * N + n];
+        const double pu = px * ux + py * uy + pz * uz;
+        pmb += pu;
+        rhob -= pu / 3.0;
+        const double utx = A[A_UB * N + n] + c2 * px;
+        const double uty = A[(A_UB + 1) * N + n] + c2 * py;
+        const double utz = A[(A_UB + 2) * N + n] + c2 * pz;
+        // u = (j + F/2)/rho
+        A[A_JB * N + n] = utx / r;
+        A[(A_JB + 1) * N + n] = uty / r;
+        A[(A_JB + 2) * N + n] = utz / r;
+        const double Fbx = A[A_FB * N + n] + 0.5 * utx / r;
+        const double Fby = A[(A_FB + 1) * N + n] + 0.5 * uty / r;
+        const double Fbz = A[(A_FB + 2) * N + n] + 0.5 * utz / r;
+        rhob -= (utx * ux + uty * uy + utz * uz) / r;
+        // F = (1/3 - rho) G, G = grad_h mu recomputed
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            if (i == kRest) continue;
+            const double m = wi(i) * R.at(3, k + czi(i), cxi(i), cyi(i));
+            if (cxi(i)) gx += cxi(i) * m;
+            if (cyi(i)) gy += cyi(i) * m;
+            if (czi(i)) gz += czi(i) * m;
+        }
+        gx *= 3.0;
+        gy *= 3.0;
+        gz *= 3.0;
+        const double c1 = 1.0 / 3.0 - r;
+        A[A_GB * N + n] = c1 * Fbx;
+        A[(A_GB + 1) * N + n] = c1 * Fby;
+        A[(A_GB + 2) * N + n] = c1 * Fbz;
+        rhob -= Fbx * gx + Fby * gy + Fbz * gz;
+        A[A_RHOB * N + n] = rhob;
+        A[A_MUB * N + n] = pmb / 3.0;  // local part of mu_bar (p_m = (1 + mu)/3)
+    });
 }
 
 // mu_bar(y) = local part (fluid) - 3 sum_i w_i c_i . G_bar(y + c_i), at every
 // node (G_bar is zero at solid nodes), into A_MUBT.
-__global__ __launch_bounds__(kBlock) void k_adj_mu(KP kp, Bufs b) {
-    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
-    if (n >= kp.N) return;
-    int x, y, z;
-    decompose(kp, n, x, y, z);
-    const bool fluid = z >= kp.z0 && z < kp.z1;
-    const Nb nb(kp, x, y, z);
+__global__ __launch_bounds__(ZCB) void k_adj_mu(KP kp, Bufs b, int cz) {
+    __shared__ double lds[4][3][ZNR];
+    int x0, y0, zs, ze;
+    ztile(kp, cz, 0, kp.nz, x0, y0, zs, ze);
     const size_t N = kp.N;
-    const double *A = (const double *)b.abuf;
-    const double *gb = A + A_GB * N;
-    double s = 0.0;
+    double *A = (double *)b.abuf;
+    ZRing<3> R;
+    R.init(kp, lds, x0, y0);
+    for (int c = 0; c < 3; ++c) R.src[c] = A + (A_GB + c) * N;
+    R.march(zs, ze, [&](int k) {
+        if (!R.own) return;
+        double s = 0.0;
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        if (i == kRest) continue;
-        const unsigned m = nb.at(cxi(i), cyi(i), czi(i));
-        double d = 0.0;
-        if (cxi(i)) d += cxi(i) * gb[m];
-        if (cyi(i)) d += cyi(i) * gb[N + m];
-        if (czi(i)) d += czi(i) * gb[2 * N + m];
-        s += wi(i) * d;
-    }
-    ((double *)b.abuf)[A_MUBT * N + n] = (fluid ? A[A_MUB * N + n] : 0.0) - 3.0 * s;
+        for (int i = 0; i < 27; ++i) {
+            if (i == kRest) continue;
+            const int p = k + czi(i);
+            double d = 0.0;
+            if (cxi(i)) d += cxi(i) * R.at(0, p, cxi(i), cyi(i));
+            if (cyi(i)) d += cyi(i) * R.at(1, p, cxi(i), cyi(i));
+            if (czi(i)) d += czi(i) * R.at(2, p, cxi(i), cyi(i));
+            s += wi(i) * d;
+        }
+        const size_t n = (size_t)k * kp.plane + R.node;
+        const bool fluid = k >= kp.z0 && k < kp.z1;
+        A[A_MUBT * N + n] = (fluid ? A[A_MUB * N + n] : 0.0) - 3.0 * s;
+    });
 }
 
 // Normalising weight sum of the wall average at solid node (x, y, zs).
@@ -463,38 +561,43 @@ __global__ __launch_bounds__(kBlock) void k_adj_wall_gather(KP kp, const double 
 // rho_bar_total(y) = [fluid: rho_bar + mu_bar mu0'(rho)] - kappa L[mu_bar_fluid](y);
 // per-node dL/dkappa = -mu_bar L[rho].  `mub` is the total mu_bar (solid
 // entries are ignored: the Laplacian's adjoint sees fluid mu_bar only).
-__global__ __launch_bounds__(kBlock) void k_adj_rho(KP kp, Bufs b, const double *mub, const double *rhob_local,
-                                                    const double *rho, double *rhobt, double *kapc) {
-    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
-    if (n >= kp.N) return;
-    int x, y, z;
-    decompose(kp, n, x, y, z);
-    const bool fluid = z >= kp.z0 && z < kp.z1;
-    const Nb nb(kp, x, y, z);
-    const double m0 = fluid ? mub[n] : 0.0;
-    const double r0 = rho[n];
-    double lm = 0.0, lr = 0.0;
+__global__ __launch_bounds__(ZCB) void k_adj_rho(KP kp, const double *mub, const double *rhob_local,
+                                                 const double *rho, double *rhobt, double *kapc, int cz) {
+    __shared__ double lds[4][2][ZNR];
+    int x0, y0, zs, ze;
+    ztile(kp, cz, 0, kp.nz, x0, y0, zs, ze);
+    ZRing<2> R;
+    R.init(kp, lds, x0, y0);
+    R.src[0] = mub;
+    R.src[1] = rho;
+    R.zmask = 1u;  // mu_bar of solid planes reads as zero
+    R.march(zs, ze, [&](int k) {
+        if (!R.own) return;
+        const bool fluid = k >= kp.z0 && k < kp.z1;
+        const double m0 = R.at(0, k, 0, 0);
+        const double r0 = R.at(1, k, 0, 0);
+        double lm = 0.0, lr = 0.0;
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        if (i == kRest) continue;
-        const unsigned m = nb.at(cxi(i), cyi(i), czi(i));
-        const int zz = (int)(m / kp.plane);
-        const bool fl = zz >= kp.z0 && zz < kp.z1;
-        lm += wi(i) * ((fl ? mub[m] : 0.0) - m0);
-        lr += wi(i) * (rho[m] - r0);
-    }
-    lm *= 6.0;
-    lr *= 6.0;
-    double out = -kp.kappa * lm;
-    if (fluid) {
-        const double d = 1.0 - kp.b * r0;
-        const double dmu0 = kp.RT / (r0 * d * d) - 2.0 * kp.a;
-        out += rhob_local[n] + m0 * dmu0;
-        kapc[n] = -m0 * lr;
-    } else {
-        kapc[n] = 0.0;
-    }
-    rhobt[n] = out;
+        for (int i = 0; i < 27; ++i) {
+            if (i == kRest) continue;
+            const int p = k + czi(i);
+            lm += wi(i) * (R.at(0, p, cxi(i), cyi(i)) - m0);
+            lr += wi(i) * (R.at(1, p, cxi(i), cyi(i)) - r0);
+        }
+        lm *= 6.0;
+        lr *= 6.0;
+        const size_t n = (size_t)k * kp.plane + R.node;
+        double out = -kp.kappa * lm;
+        if (fluid) {
+            const double d = 1.0 - kp.b * r0;
+            const double dmu0 = kp.RT / (r0 * d * d) - 2.0 * kp.a;
+            out += rhob_local[n] + m0 * dmu0;
+            kapc[n] = -m0 * lr;
+        } else {
+            kapc[n] = 0.0;
+        }
+        rhobt[n] = out;
+    });
 }
 
 // Solid nodes: rho_ave_bar = W'(rho_ave) rho_bar(x_s), and the per-node
@@ -688,6 +791,13 @@ template <class Fn> hipError_t dispatch(int prec, Fn &&fn) {
     }
 }
 
+// Grid of the z-marching adjoint kernels over planes [zlo, zhi).
+constexpr int kZChunk = 16;
+dim3 zgrid(const KP &kp, int zlo, int zhi) {
+    const unsigned ntx = (kp.nx + ZTX - 1) / ZTX, nty = (kp.ny + ZTY - 1) / ZTY;
+    return dim3(ntx * nty, (unsigned)((zhi - zlo + kZChunk - 1) / kZChunk));
+}
+
 // The chain from mu_bar (local parts already in A_MUB, G_bar in A_GB) to
 // rho_bar_total (A_RHOBT) with walls, and the kappa / wet accumulation.
 hipError_t chain_tail(hipStream_t s, const KP &kp, const Bufs &b, bool with_gradient_transpose,
@@ -696,12 +806,13 @@ hipError_t chain_tail(hipStream_t s, const KP &kp, const Bufs &b, bool with_grad
     double *A = (double *)b.abuf;
     const unsigned gN = nblocks(N), gw = nblocks(2 * (size_t)kp.plane);
     double *mub_tot = A + A_MUB * N;
+    const dim3 gall = zgrid(kp, 0, kp.nz);
     if (with_gradient_transpose) {
-        k_adj_mu<<<gN, kBlock, 0, s>>>(kp, b);
+        k_adj_mu<<<gall, ZCB, 0, s>>>(kp, b, kZChunk);
         mub_tot = A + A_MUBT * N;
     }
     if (kp.walls) k_adj_wall_gather<<<gw, kBlock, 0, s>>>(kp, mub_tot, mub_tot);
-    k_adj_rho<<<gN, kBlock, 0, s>>>(kp, b, mub_tot, A + A_RHOB * N, b.rho, A + A_RHOBT * N, A + A_KAPC * N);
+    k_adj_rho<<<gall, ZCB, 0, s>>>(kp, mub_tot, A + A_RHOB * N, b.rho, A + A_RHOBT * N, A + A_KAPC * N, kZChunk);
     const double *wetc = nullptr;
     if (kp.walls) {
         k_adj_wall_rho_solid<<<gw, kBlock, 0, s>>>(kp, b.rho, A + A_RHOBT * N, A + A_RAVEB * N, A + A_WETC * N);
@@ -762,7 +873,7 @@ hipError_t launch_adj_step(hipStream_t s, int prec, const KP &kp, const Bufs &b,
     return dispatch(prec, [&](auto pc) {
         constexpr int P = decltype(pc)::value;
         k_adj_collide<P><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
-        k_adj_phi<P><<<gf, kBlock, 0, s>>>(kp, b);
+        k_adj_phi<P><<<zgrid(kp, kp.z0, kp.z1), ZCB, 0, s>>>(kp, b, kZChunk);
         hipError_t r = chain_tail(s, kp, b, true, A + A_NUC * (size_t)kp.N);
         if (r != hipSuccess) return r;
         k_adj_final<P><<<gf, kBlock, 0, s>>>(kp, b, b.lam[1 - lcur]);
