@@ -36,6 +36,9 @@ CASES = [
     ("walls phi 1.4", (12, 8, 9), True, dict(wet_mode=1, wet_value=1.4)),
     ("walls drho 1.2", (12, 8, 9), True, dict(wet_mode=2, wet_value=1.2)),
     ("walls neutral", (10, 7, 8), True, dict(wet_mode=0)),
+    # several tiles and z-chunks of the z-marching kernels, ragged edges
+    ("periodic multi-tile 37x11x35", (35, 11, 37), False, {}),
+    ("walls phi 1.3 multi-tile 33x10x34", (34, 10, 33), True, dict(wet_mode=1, wet_value=1.3)),
 ]
 
 
