@@ -87,13 +87,19 @@ typedef struct lbfe_params {
     int32_t check_every; /* lbfe_step checks the divergence flag every this
                             many steps (>= 1) and at the end               */
     int32_t adjoint;     /* 1: the workspace also holds adjoint buffers    */
+    double wall_u[4];    /* tangential velocities (ux, uy) of the bottom
+                            (z = 0) and top (z = nz-1) walls, moving-wall
+                            test of Sec. III B: momentum-corrected halfway
+                            bounce-back; |u| <= 0.3; nonzero needs
+                            walls_z = 1 and adjoint = 0; 0 = resting walls */
 } lbfe_params;
 
 typedef struct lbfe_ctx lbfe_ctx;
 
 /* Fill *p with the paper's defaults (Sec. III): a = 9/392, b = 2/21, R = 1,
  * T = 0.7 T_c, kappa = 0.02, nu = 0.15, all omega_k = 1, corr4 on,
- * periodic 32^3, neutral wetting, FP64, check_every = 100, adjoint off. */
+ * periodic 32^3, neutral wetting, resting walls, FP64, check_every = 100,
+ * adjoint off. */
 int lbfe_params_default(lbfe_params *p);
 
 /* Coexistence pair of the vdW EOS at temperature T from equal chemical

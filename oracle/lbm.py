@@ -56,6 +56,9 @@ class Params:
     rho_v: float = 0.0
     wet_mode: int = NEUTRAL
     wet_value: float = 1.0
+    # tangential velocities (ux, uy) of the bottom (z = 0) and top (z = nz-1)
+    # walls; moving walls use the momentum-corrected halfway bounce-back
+    wall_u: tuple = (0.0, 0.0, 0.0, 0.0)
 
     def coexistence(self):
         if self.rho_l > 0 and self.rho_v > 0:
@@ -324,16 +327,43 @@ def aux_fields(f, p: Params):
                 Q=(Q200, Q020, Q002, Q220, Q202, Q022), omega1=om1, s=s)
 
 
-def stream(fs, p: Params):
+def stream(fs, p: Params, rho=None, pm=None):
     """Eq. (10): f_i(x, t+1) = f*_i(x - c_i); with walls the halfway
-    bounce-back f_i(x, t+1) = f*_opp(i)(x) when x - c_i is solid."""
+    bounce-back f_i(x, t+1) = f*_opp(i)(x) when x - c_i is solid.
+
+    Moving walls (the moving-wall droplet test of Sec. III B, whose scheme
+    the paper cites without writing it out): the reflected population takes
+    the odd part of the model's own equilibrium at the wall velocity u_w,
+        f_i(x, t+1) = f*_o(x) - [f^eq_o - f^eq_i](rho(x), p_m(x), u_w),
+    o = opp(i), with f^eq the generalized equilibrium of Eq. (20) at the
+    fluid node's rho and p_m.  A fluid moving with the wall is then left
+    unchanged by the wall; for p_m = rho c_s^2 the bracket is, to first order
+    in u_w, the familiar 2 w_o rho c_o . u_w / c_s^2."""
     s = fluid_mask(p)
+    moving = p.walls_z and any(v != 0.0 for v in p.wall_u)
+    if moving:
+        shape = tuple(fs.shape[1:])
+
+        def feq_at(ux, uy):
+            uw = torch.zeros((3,) + shape, dtype=DT)
+            uw[0] = ux
+            uw[1] = uy
+            return populations_from_central(equilibrium_central(rho, pm), uw)
+
+        feq_b = feq_at(p.wall_u[0], p.wall_u[1])  # bottom wall (z = 0)
+        feq_t = feq_at(p.wall_u[2], p.wall_u[3])  # top wall (z = nz-1)
     out = []
     for i, c in enumerate(C):
         pulled = at(fs[i], (-c[0], -c[1], -c[2]))
         if p.walls_z:
             src_fluid = at(s, (-c[0], -c[1], -c[2])) > 0
-            pulled = torch.where(src_fluid, pulled, fs[OPP[i]])
+            back = fs[OPP[i]]
+            if moving and c[2] != 0:
+                # x - c_i is solid only across a z wall: c_z > 0 reflects at
+                # the bottom wall, c_z < 0 at the top wall
+                fe = feq_b if c[2] > 0 else feq_t
+                back = back - (fe[OPP[i]] - fe[i])
+            pulled = torch.where(src_fluid, pulled, back)
             pulled = pulled * s
         out.append(pulled)
     return torch.stack(out)
@@ -347,7 +377,7 @@ def step(f, p: Params, return_aux=False):
     k = central_moments(f, A["u"])
     ks = collide(k, A["F"], A["Q"], A["pm"], w)
     fs = populations_from_central(ks, A["u"])
-    fn = stream(fs, p)
+    fn = stream(fs, p, A["rho"], A["pm"])
     return (fn, A) if return_aux else fn
 
 

@@ -109,6 +109,13 @@ std::string validate(const lbfe_params &p) {
     if (p.rho_l > 0 && !(p.rho_l > p.rho_v)) return "rho_l must exceed rho_v";
     if (p.check_every < 1) return "check_every must be >= 1";
     if (p.adjoint != 0 && p.adjoint != 1) return "adjoint must be 0 or 1";
+    bool moving = false;
+    for (int k = 0; k < 4; ++k) {
+        if (!finite(p.wall_u[k]) || std::fabs(p.wall_u[k]) > 0.3) return "wall_u must be finite with |u| <= 0.3";
+        moving = moving || p.wall_u[k] != 0.0;
+    }
+    if (moving && !p.walls_z) return "moving walls need walls_z = 1";
+    if (moving && p.adjoint) return "the adjoint does not cover moving walls";
     return "";
 }
 
@@ -259,6 +266,8 @@ int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out) {
     k.nu = q.nu;
     for (int i = 0; i < 11; ++i) k.om[i] = q.omega[i];
     k.corr4 = q.corr4;
+    for (int i = 0; i < 4; ++i) k.wall_u[i] = q.wall_u[i];
+    k.moving = q.wall_u[0] != 0.0 || q.wall_u[1] != 0.0 || q.wall_u[2] != 0.0 || q.wall_u[3] != 0.0;
     k.wet_mode = q.wet_mode;
     k.wet_value = q.wet_value;
     k.lo = 0.05 * q.rho_l + 0.95 * q.rho_v;
@@ -275,7 +284,7 @@ int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out) {
     // SIMD; measured on gfx950 it is on par in FP64 and slower in the FP32
     // and FP16 forms.
     const char *fu = std::getenv("LBFE_FUSED");
-    c->fused = fu && fu[0] == '1';
+    c->fused = fu && fu[0] == '1' && !k.moving;  // the fused kernel has resting walls only
     *out = c;
     return LBFE_OK;
 }

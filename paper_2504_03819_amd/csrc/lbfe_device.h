@@ -332,8 +332,8 @@ __device__ inline void collide(real (&k)[27], const Rates<real> &R, real Fx, rea
 // transform.  f: the arriving populations in, post-collision out.
 // ---------------------------------------------------------------------------
 template <class real>
-__device__ inline void collide_node(const KP &kp, real (&f)[27], double mu, real Fx, real Fy, real Fz, real q200,
-                                    real q020, real q002) {
+__device__ inline double collide_node(const KP &kp, real (&f)[27], double mu, real Fx, real Fy, real Fz, real q200,
+                                      real q020, real q002) {
     double rd;
     real jx, jy, jz;
     moments(f, rd, jx, jy, jz);
@@ -357,6 +357,22 @@ __device__ inline void collide_node(const KP &kp, real (&f)[27], double mu, real
     cm_forward(f, ux, uy, uz);
     collide(f, R, Fx, Fy, Fz, pm, q200, q020, q002, q220, q202, q022);
     cm_inverse(f, ux, uy, uz);
+    return rd;
+}
+
+// Populations of the generalized equilibrium of Eq. (20) at (rho, p_m) and
+// the tangential wall velocity (ux, uy, 0): the moving-wall bounce-back
+// gives the population reflected from direction i the correction
+// -(feq_i - feq_opp(i)), so that a fluid moving with the wall is unchanged.
+template <class real>
+__device__ inline void wall_equilibrium(real rho, real pm, real ux, real uy, real (&feq)[27]) {
+#pragma unroll
+    for (int i = 0; i < 27; ++i) feq[i] = 0;
+    feq[K(0, 0, 0)] = rho;
+    feq[K(2, 0, 0)] = feq[K(0, 2, 0)] = feq[K(0, 0, 2)] = pm;
+    feq[K(2, 2, 0)] = feq[K(2, 0, 2)] = feq[K(0, 2, 2)] = pm * (real)(1.0 / 3.0);
+    feq[K(2, 2, 2)] = pm * (real)(1.0 / 9.0);
+    cm_inverse(feq, ux, uy, (real)0);
 }
 
 }  // namespace lbfe

@@ -27,6 +27,8 @@ struct KP {
     int corr4, wet_mode;
     double wet_value, lo, hi;  // wetting value and contact-line window
     int xcd_remap;             // map consecutive tiles onto one XCD
+    double wall_u[4];          // (ux, uy) of the bottom and top walls
+    int moving;                // some wall velocity is nonzero
 };
 
 // Device pointers of one context (all inside the caller's workspace).

@@ -115,7 +115,8 @@ __global__ __launch_bounds__(kBlock) void k_mu(KP kp, const double *rho, double 
 }
 
 // Fused collide + stream of one fluid node (push: f*_i(x) -> x + c_i, or
-// -> slot opp(i) of x when x + c_i is solid: halfway bounce-back).
+// -> slot opp(i) of x when x + c_i is solid: halfway bounce-back, with the
+// moving-wall correction when the walls move).
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_collide(KP kp, const void *fin_q, void *fout_q, const double *mu,
                                                     const void *Fq, const void *Qq) {
@@ -134,11 +135,25 @@ __global__ __launch_bounds__(kBlock) void k_collide(KP kp, const void *fin_q, vo
 #pragma unroll
     for (int i = 0; i < 27; ++i) f[i] = fin.ld(i, row, (unsigned)x);
     const real *F = (const real *)Fq, *Qa = (const real *)Qq;
-    collide_node(kp, f, mu[n], F[n], F[kp.N + n], F[2 * (size_t)kp.N + n], Qa[n], Qa[kp.N + n],
-                 Qa[2 * (size_t)kp.N + n]);
+    const double rd = collide_node(kp, f, mu[n], F[n], F[kp.N + n], F[2 * (size_t)kp.N + n], Qa[n], Qa[kp.N + n],
+                                   Qa[2 * (size_t)kp.N + n]);
 
     const bool wall_lo = kp.walls && z == 1;
     const bool wall_hi = kp.walls && z == kp.nz - 2;
+    if (kp.moving && (wall_lo || wall_hi)) {
+        // moving walls: the reflected populations take the odd part of the
+        // equilibrium at the wall velocity (fluid rho and p_m of this node)
+        const real rho = (real)rd, pm = (real)((1.0 + mu[n]) * (1.0 / 3.0));
+        real fb[27], ft[27];
+        wall_equilibrium(rho, pm, (real)kp.wall_u[0], (real)kp.wall_u[1], fb);
+        wall_equilibrium(rho, pm, (real)kp.wall_u[2], (real)kp.wall_u[3], ft);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const int cz = czi(i);
+            if (cz < 0 && wall_lo) f[i] -= fb[i] - fb[26 - i];
+            if (cz > 0 && wall_hi) f[i] -= ft[i] - ft[26 - i];
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int cz = czi(i);

@@ -35,6 +35,7 @@ class Params(ctypes.Structure):
         ("corr4", c_int32), ("wet_mode", c_int32), ("wet_value", c_double),
         ("rho_l", c_double), ("rho_v", c_double),
         ("check_every", c_int32), ("adjoint", c_int32),
+        ("wall_u", c_double * 4),
     ]
 
 
@@ -92,9 +93,10 @@ def default_params(**kw):
     rc = lib().lbfe_params_default(byref(p))
     assert rc == OK
     for k, v in kw.items():
-        if k == "omega":
+        if k in ("omega", "wall_u"):
+            arr = getattr(p, k)
             for i, w in enumerate(v):
-                p.omega[i] = float(w)
+                arr[i] = float(w)
         elif k == "precision" and isinstance(v, str):
             p.precision = PRECISIONS[v]
         else:

@@ -68,6 +68,8 @@ def test_coexistence_matches_oracle_maxwell():
     dict(precision=7), dict(wet_mode=1, wet_value=0.0), dict(wet_mode=2, wet_value=-0.5), dict(wet_mode=5),
     dict(rho_l=7.0), dict(rho_l=1.0, rho_v=2.0), dict(check_every=0), dict(corr4=2), dict(b=0.0),
     dict(nx=2048, ny=2048, nz=1024), dict(nx=32768, ny=16384, nz=1),
+    dict(wall_u=(0.1, 0.0, 0.0, 0.0)), dict(walls_z=1, wall_u=(0.0, 0.0, 0.31, 0.0)),
+    dict(walls_z=1, adjoint=1, wall_u=(0.1, 0.0, 0.1, 0.0)), dict(walls_z=1, wall_u=(float("nan"), 0.0, 0.0, 0.0)),
 ])
 def test_invalid_parameters_rejected_before_device(override):
     p = lbfe.default_params()

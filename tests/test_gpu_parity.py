@@ -41,6 +41,8 @@ CASES = [
     ("walls neutral", (12, 9, 7), True, dict(wet_mode=0)),
     ("walls phi 1.6", (12, 9, 7), True, dict(wet_mode=1, wet_value=1.6)),
     ("walls drho 1.8", (12, 9, 7), True, dict(wet_mode=2, wet_value=1.8)),
+    ("moving walls phi 1.4", (12, 9, 7), True, dict(wet_mode=1, wet_value=1.4, wall_u=(0.08, -0.03, -0.05, 0.02))),
+    ("moving walls, one fluid plane", (3, 9, 7), True, dict(wall_u=(0.1, 0.0, -0.1, 0.05))),
 ]
 
 
@@ -102,6 +104,29 @@ def test_trajectory_sessile_droplet_walls():
     o = oracle_fields(f, p)
     errs = {k: rel_err(g[k], o[k]) for k in o}
     say(f"sessile t=30: f={e:.2e} " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    assert e < TOL and all(v < TOL for v in errs.values())
+
+
+def test_trajectory_moving_walls():
+    """Droplet between walls moving in opposite directions (the moving-wall
+    boundary of the Sec. III B test), 30 steps against the oracle."""
+    T = eos.temperature(0.7)
+    shape = (14, 12, 16)
+    sim = make_sim(nx=16, ny=12, nz=14, T=T, walls_z=1, wall_u=(0.1, 0.0, -0.1, 0.02),
+                   omega=[1.0, 1.0, 1.0, 0.5] + [1.0] * 7)
+    p = oracle_params(sim)
+    rho0 = droplet_rho(shape, T, radius=4.0, noise=0)
+    rho0[0] = rho0[-1] = sim.rho_v
+    sim.init_density(torch.tensor(rho0))
+    f = lbm.init(torch.tensor(rho0), p)
+    sim.step(30)
+    f = lbm.run(f, p, 30)
+    fg = sim.populations().cpu()
+    e = rel_err(fg[:, 1:-1], f[:, 1:-1])
+    g = gpu_fields(sim)
+    o = oracle_fields(f, p)
+    errs = {k: rel_err(g[k], o[k]) for k in o}
+    say(f"moving walls t=30: f={e:.2e} " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     assert e < TOL and all(v < TOL for v in errs.values())
 
 

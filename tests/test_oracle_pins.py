@@ -457,3 +457,83 @@ def test_shear_wave_decay_gives_nu():
     a200 = amp(lbm.run(f, p, 150))
     rate = math.log(a200 / a50) / 150
     assert abs(rate / (-nu * k * k) - 1) < 2e-3
+
+
+# ---------------------------------------------------------------------------
+# Moving walls (the moving-wall droplet test of Sec. III B)
+# ---------------------------------------------------------------------------
+def _moving_params(nx, ny, nz, wall_u):
+    T = 0.7 * eos.critical_point(eos.PAPER["a"], eos.PAPER["b"], 1.0)[1]
+    return lbm.Params(nx, ny, nz, walls_z=True, T=T, omega=[1.0, 1.0, 1.0, 0.5] + [1.0] * 7,
+                      wall_u=tuple(wall_u)), T
+
+
+@pytest.mark.parametrize("phase", ["liquid", "vapour"])
+def test_moving_walls_leave_a_comoving_fluid_unchanged(phase):
+    """A uniform fluid moving with both walls is a fixed point of the step:
+    the reflected populations take exactly the equilibrium's odd part at the
+    wall velocity (any error in sign, factor, wall side or the p_m structure
+    of the correction breaks this at the first step)."""
+    U = (0.1, -0.03)
+    p, T = _moving_params(3, 4, 9, (U[0], U[1], U[0], U[1]))
+    rl, rv = eos.maxwell(p.a, p.b, p.R, T)
+    r = rl if phase == "liquid" else rv
+    rho = torch.full((9, 4, 3), r, dtype=torch.float64)
+    u0 = torch.zeros((3, 9, 4, 3), dtype=torch.float64)
+    u0[0], u0[1] = U
+    f = lbm.init(rho, p, u0)
+    f1 = lbm.step(f, p)
+    assert float((f1 - f).abs().max() / f.abs().max()) < 1e-13
+
+
+def test_moving_walls_couette_profile_is_linear():
+    """Walls at -U (bottom) and +U (top) in a uniform liquid: the steady
+    velocity is linear between the walls located half a link beyond the
+    first and last fluid planes, u_x(z) = -U + 2U (z - 1/2)/(nz - 2), with
+    no slip; the mass is conserved."""
+    U = 1e-3
+    nz = 6  # four fluid planes: the start-up transient decays by ~20x per 100 steps
+    p, T = _moving_params(1, 1, nz, (-U, 0.0, U, 0.0))
+    rl, _ = eos.maxwell(p.a, p.b, p.R, T)
+    f = lbm.init(torch.full((nz, 1, 1), rl, dtype=torch.float64), p)
+    m0 = float(lbm.aux_fields(f, p)["rho"][1:-1].sum())
+    for _ in range(500):
+        f = lbm.step(f, p)
+    A = lbm.aux_fields(f, p)
+    z = torch.arange(1, nz - 1, dtype=torch.float64)
+    exact = -U + 2 * U * (z - 0.5) / (nz - 2)
+    ux = A["u"][0][1:-1, 0, 0]
+    assert float((ux - exact).abs().max()) < 1e-6 * U
+    assert float(A["u"][1].abs().max()) < 1e-15 and float(A["u"][2][1:-1].abs().max()) < 1e-13
+    assert abs(float(A["rho"][1:-1].sum()) - m0) < 1e-12 * m0
+
+
+def test_moving_wall_correction_reduces_to_the_ideal_gas_form():
+    """With p_m = rho c_s^2 the bracket f^eq_o - f^eq_i at the wall velocity
+    is, to first order in u_w, the textbook 2 w_o rho c_o . u_w / c_s^2."""
+    rho = torch.tensor([[[2.3]]], dtype=torch.float64)
+    pm = rho / 3.0
+    eps = 1e-6
+    uw = torch.zeros((3, 1, 1, 1), dtype=torch.float64)
+    uw[0], uw[1] = eps, -0.5 * eps
+    feq = lbm.populations_from_central(lbm.equilibrium_central(rho, pm), uw)
+    for o, c in enumerate(C):
+        i = OPP[o]
+        got = float(feq[o] - feq[i])
+        want = 2.0 * float(W_EXACT[o]) * 2.3 * (c[0] * eps - 0.5 * c[1] * eps) * 3.0
+        assert abs(got - want) < 1e-9 * eps + 1e-6 * abs(want)
+
+
+def test_mass_conservation_with_moving_walls():
+    """A droplet between walls moving in opposite directions keeps its mass
+    to round-off (the corrections of the reflected populations cancel)."""
+    nz, ny, nx = 12, 10, 11
+    p, T = _moving_params(nx, ny, nz, (0.05, 0.02, -0.04, 0.0))
+    rl, rv = eos.maxwell(p.a, p.b, p.R, T)
+    rho = torch.tensor(phys.tanh_droplet((nz, ny, nx), (nx / 2, ny / 2, 0.5), 4.5, rl, rv), dtype=DT)
+    f = lbm.init(rho, p)
+    m0 = float(lbm.aux_fields(f, p)["rho"][1:-1].sum())
+    for _ in range(8):
+        f = lbm.step(f, p)
+    m1 = float(lbm.aux_fields(f, p)["rho"][1:-1].sum())
+    assert abs(m1 - m0) < 1e-12 * m0
