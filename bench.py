@@ -38,11 +38,11 @@ def alg_bytes_per_node(form):
 
 
 def kernel_source_hash():
-    """Hash of the sources the collide-stream kernel is built from (the
-    counter file is ignored once they change)."""
+    """Hash of the sources the step's kernels are built from (the counter
+    file is ignored once they change)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2504_03819_amd", "csrc")
-    for name in ("lbfe_kernels.hip", "lbfe_device.h", "lbfe_internal.h"):
+    for name in ("lbfe_kernels.hip", "lbfe_chain.hip", "lbfe_device.h", "lbfe_internal.h"):
         h.update(open(os.path.join(csrc, name), "rb").read())
     return h.hexdigest()[:16]
 
@@ -71,8 +71,15 @@ def workload(name, lbfe, torch):
         T = 0.7 * 8 * (9 / 392) / (27 * (2 / 21))
         rl, rv = lbfe.coexistence(9 / 392, 2 / 21, 1.0, T)
         rho, u = inputs.sessile_droplet(rl, rv)
-        desc = "sessile droplet 192x192x96, walls z=0,95, r=32, phi=1.0, T=0.7Tc"
-        return dict(nx=192, ny=192, nz=96, T=T, walls_z=1, wet_mode=1, wet_value=1.0), rho, u, desc
+        desc = "sessile droplet 192x192x96, walls z=0,95, r=32, phi=1.0, T=0.7Tc, omega3=0.5"
+        return dict(nx=192, ny=192, nz=96, T=T, walls_z=1, wet_mode=1, wet_value=1.0,
+                    omega=[1.0, 1.0, 1.0, 0.5] + [1.0] * 7), rho, u, desc
+    if name == "moving_walls":
+        T = 0.8 * 8 * (9 / 392) / (27 * (2 / 21))
+        rl, rv = lbfe.coexistence(9 / 392, 2 / 21, 1.0, T)
+        rho = inputs.sphere((128, 128, 128), (64, 64, 64), 30.0, rl, rv)
+        desc = "droplet 128^3 r=30 between walls moving at U=0.1 (x), T=0.8Tc"
+        return dict(nx=128, ny=128, nz=128, T=T, walls_z=1, wall_u=(0.1, 0.0, 0.1, 0.0)), rho, None, desc
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -114,7 +121,6 @@ def time_adjoint(lbfe, torch, steps=20, form="fp32"):
     recomputation of the auxiliary fields of f(t)); the forward recompute
     that a checkpointed run adds is timed separately."""
     geom, rho, u, desc = workload("wetting", lbfe, torch)
-    geom = dict(geom, omega=[1.0, 1.0, 1.0, 0.5] + [1.0] * 7)
     sim = lbfe.Simulation(device="cuda:0", precision=form, adjoint=1, **geom)
     nfluid = sim.params.nx * sim.params.ny * (sim.params.nz - 2)
     sim.init_density(torch.tensor(rho))
@@ -274,6 +280,14 @@ def main():
         if c.get("source_hash") == kernel_source_hash() and c.get("workload") == args.workload \
                 and c.get("form") == head:
             roof["traffic"] = c.get("bytes_per_launch")
+            # achieved HBM fraction of the whole step: calibrated counter
+            # bytes of every kernel of one step over the measured step time
+            ff, wf = c["copy_fetch_factor"], c["copy_write_factor"]
+            step_kernels = ("k_moments", "k_chain", "k_collide", "k_wall_rho")
+            tb = sum(v * ff for k, v in c["kernels"]["fetch_kib"].items() if any(s in k for s in step_kernels))
+            tb += sum(v * wf for k, v in c["kernels"]["write_kib"].items() if any(s in k for s in step_kernels))
+            roof["step_traffic"] = tb * 1024.0
+            roof["step_achieved_frac"] = round(tb * 1024.0 / (r["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     adj = None
     if not args.no_adjoint:
         print("[bench] timing the adjoint (wetting workload, FP32)", file=sys.stderr, flush=True)
