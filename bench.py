@@ -239,13 +239,15 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calib", action="store_true", help="run a 1 GiB device copy first (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--adjoint-only", action="store_true", help="time only the adjoint leg, print its JSON")
+    ap.add_argument("--adjoint-steps", type=int, default=20)
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, form=args.forms.split(",")[0], workload_name=args.workload,
                            out_path=COUNTERS)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        sys.stderr.write("bench.py: this build runs on one GPU only; a multi-GPU (z-slab) decomposition "
+        sys.stderr.write("bench.py: runs on one GPU only; a multi-GPU (z-slab) decomposition "
                          "is designed but not built, so --gpus must be 1.\n")
         sys.exit(2)
 
@@ -254,6 +256,9 @@ def main():
     if not torch.cuda.is_available():
         sys.stderr.write("bench.py needs a GPU\n")
         sys.exit(1)
+    if args.adjoint_only:
+        print(json.dumps(time_adjoint(lbfe, torch, steps=args.adjoint_steps)), flush=True)
+        return
     geom, rho, u, desc = workload(args.workload, lbfe, torch)
     if args.copy_calib:
         copy_calibration(torch)
@@ -291,7 +296,7 @@ def main():
     adj = None
     if not args.no_adjoint:
         print("[bench] timing the adjoint (wetting workload, FP32)", file=sys.stderr, flush=True)
-        adj = time_adjoint(lbfe, torch)
+        adj = time_adjoint(lbfe, torch, steps=args.adjoint_steps)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

@@ -669,10 +669,17 @@ template <int P> __global__ __launch_bounds__(kBlock) void k_adj_final(KP kp, Bu
 __global__ __launch_bounds__(kBlock) void k_adj_reduce_part(unsigned n, const double *a0, const double *a1,
                                                             const double *a2, double *part) {
     __shared__ double s[3][kBlock];
-    const unsigned i = blockIdx.x * kBlock + threadIdx.x;
-    s[0][threadIdx.x] = (a0 && i < n) ? a0[i] : 0.0;
-    s[1][threadIdx.x] = (a1 && i < n) ? a1[i] : 0.0;
-    s[2][threadIdx.x] = (a2 && i < n) ? a2[i] : 0.0;
+    // a fixed grid-stride assignment: the same sums in the same order on
+    // every call
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+    for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        if (a0) v0 += a0[i];
+        if (a1) v1 += a1[i];
+        if (a2) v2 += a2[i];
+    }
+    s[0][threadIdx.x] = v0;
+    s[1][threadIdx.x] = v1;
+    s[2][threadIdx.x] = v2;
     __syncthreads();
     for (int h = kBlock / 2; h > 0; h >>= 1) {
         if ((int)threadIdx.x < h)
@@ -791,6 +798,8 @@ template <class Fn> hipError_t dispatch(int prec, Fn &&fn) {
     }
 }
 
+constexpr unsigned kReduceBlocks = 1024;  // blocks of the gradient reduction
+
 // Grid of the z-marching adjoint kernels over planes [zlo, zhi).
 constexpr int kZChunk = 16;
 dim3 zgrid(const KP &kp, int zlo, int zhi) {
@@ -820,8 +829,9 @@ hipError_t chain_tail(hipStream_t s, const KP &kp, const Bufs &b, bool with_grad
         wetc = A + A_WETC * N;
     }
     double *part = b.agrad + 8;
-    k_adj_reduce_part<<<gN, kBlock, 0, s>>>((unsigned)N, A + A_KAPC * N, wetc, nuc, part);
-    k_adj_reduce_final<<<1, kBlock, 0, s>>>(gN, part, b.agrad);
+    const unsigned gr = gN < kReduceBlocks ? gN : kReduceBlocks;
+    k_adj_reduce_part<<<gr, kBlock, 0, s>>>((unsigned)N, A + A_KAPC * N, wetc, nuc, part);
+    k_adj_reduce_final<<<1, kBlock, 0, s>>>(gr, part, b.agrad);
     return hipGetLastError();
 }
 
