@@ -115,8 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_mu(KP kp, const double *rho, double 
 }
 
 // Fused collide + stream of one fluid node (push: f*_i(x) -> x + c_i, or
-// -> slot opp(i) of x when x + c_i is solid: halfway bounce-back, with the
-// moving-wall correction when the walls move).
+// -> slot opp(i) of x when x + c_i is solid: halfway bounce-back).
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_collide(KP kp, const void *fin_q, void *fout_q, const double *mu,
                                                     const void *Fq, const void *Qq) {
@@ -135,25 +134,11 @@ __global__ __launch_bounds__(kBlock) void k_collide(KP kp, const void *fin_q, vo
 #pragma unroll
     for (int i = 0; i < 27; ++i) f[i] = fin.ld(i, row, (unsigned)x);
     const real *F = (const real *)Fq, *Qa = (const real *)Qq;
-    const double rd = collide_node(kp, f, mu[n], F[n], F[kp.N + n], F[2 * (size_t)kp.N + n], Qa[n], Qa[kp.N + n],
-                                   Qa[2 * (size_t)kp.N + n]);
+    collide_node(kp, f, mu[n], F[n], F[kp.N + n], F[2 * (size_t)kp.N + n], Qa[n], Qa[kp.N + n],
+                 Qa[2 * (size_t)kp.N + n]);
 
     const bool wall_lo = kp.walls && z == 1;
     const bool wall_hi = kp.walls && z == kp.nz - 2;
-    if (kp.moving && (wall_lo || wall_hi)) {
-        // moving walls: the reflected populations take the odd part of the
-        // equilibrium at the wall velocity (fluid rho and p_m of this node)
-        const real rho = (real)rd, pm = (real)((1.0 + mu[n]) * (1.0 / 3.0));
-        real fb[27], ft[27];
-        wall_equilibrium(rho, pm, (real)kp.wall_u[0], (real)kp.wall_u[1], fb);
-        wall_equilibrium(rho, pm, (real)kp.wall_u[2], (real)kp.wall_u[3], ft);
-#pragma unroll
-        for (int i = 0; i < 27; ++i) {
-            const int cz = czi(i);
-            if (cz < 0 && wall_lo) f[i] -= fb[i] - fb[26 - i];
-            if (cz > 0 && wall_hi) f[i] -= ft[i] - ft[26 - i];
-        }
-    }
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int cz = czi(i);
@@ -161,6 +146,39 @@ __global__ __launch_bounds__(kBlock) void k_collide(KP kp, const void *fin_q, vo
             fout.st(26 - i, row, (unsigned)x, f[i]);
         else
             fout.st(i, nb.row(cyi(i), cz), nb.xo(cxi(i)), f[i]);
+    }
+}
+
+// Moving walls (after k_collide): the populations reflected at a wall of
+// velocity u_w take the odd part of the Eq. (20) equilibrium at u_w,
+// f_opp(i)(x, t+1) = f*_i(x) - [f^eq_i - f^eq_opp(i)](rho(x), p_m(x), u_w), for
+// the first and last fluid planes (2 nx ny threads).  rho and mu are those
+// of f(t), the state k_collide collided.
+template <int P> __global__ __launch_bounds__(kBlock) void k_wall_move(KP kp, void *fq, const double *rho,
+                                                                       const double *mu) {
+    using real = real_t<P>;
+    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= 2 * kp.plane) return;
+    const int side = idx >= kp.plane;  // 0: next to the bottom wall, 1: top
+    const unsigned p = idx - (side ? kp.plane : 0u);
+    const int z = side ? kp.nz - 2 : 1;
+    if (side && z == 1) return;  // one fluid plane: both walls handled by side 0
+    const unsigned y = p / (unsigned)kp.nx, x = p - y * (unsigned)kp.nx;
+    const size_t n = (size_t)z * kp.plane + p;
+    const unsigned row = (unsigned)z * (unsigned)kp.ny + y;
+    const Pops<P> f(fq, kp);
+    const real r = (real)rho[n], pm = (real)((1.0 + mu[n]) * (1.0 / 3.0));
+    real fe[27];
+    for (int w = 0; w < 2; ++w) {  // bottom, top
+        const bool hit = w == 0 ? z == 1 : z == kp.nz - 2;
+        if (!hit) continue;
+        wall_equilibrium(r, pm, (real)kp.wall_u[2 * w], (real)kp.wall_u[2 * w + 1], fe);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const int cz = czi(i);
+            if ((w == 0 && cz < 0) || (w == 1 && cz > 0))
+                f.st(26 - i, row, x, f.ld(26 - i, row, x) - (fe[i] - fe[26 - i]));
+        }
     }
 }
 
@@ -358,6 +376,7 @@ hipError_t step_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur, bool f
         if (e != hipSuccess) return e;
     } else {
         k_collide<P><<<nblocks(kp.nfluid), kBlock, 0, s>>>(kp, b.f[cur], b.f[1 - cur], b.mu, b.F, b.Q);
+        if (kp.moving) k_wall_move<P><<<gw, kBlock, 0, s>>>(kp, b.f[1 - cur], b.rho, b.mu);
     }
     mark(3);
     if (fused && kp.walls) k_wall_rho<<<gw, kBlock, 0, s>>>(kp, b.rho);
