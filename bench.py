@@ -156,6 +156,58 @@ def time_adjoint(lbfe, torch, steps=20, form="fp32"):
     return out
 
 
+def time_collision_adjoint(lbfe, torch, forward=5000, adjoint=500, snapshots=8):
+    """512^3 head-on collision in FP32: `forward` steps, then the adjoint of
+    the last `adjoint` steps from the stored state f(T - adjoint) with the
+    binomial checkpoint schedule (`snapshots` states held), loss
+    L = sum (rho_T - rho_0)^2.  Reports forward and backward times, the
+    recomputed steps and the peak device memory."""
+    from paper_2504_03819_amd.autograd import reverse_binomial
+    n = 512
+    T = 0.85 * 8 * (9 / 392) / (27 * (2 / 21))
+    rl, rv = lbfe.coexistence(9 / 392, 2 / 21, 1.0, T)
+    from paper_2504_03819_amd import inputs
+    rho0, u0 = inputs.head_on_collision(rl, rv)
+    torch.cuda.reset_peak_memory_stats()
+    sim = lbfe.Simulation(device="cuda:0", nx=n, ny=n, nz=n, T=T, precision="fp32", adjoint=1, check_every=500)
+    r0 = torch.tensor(rho0, device="cuda:0")
+    sim.init_density(r0, torch.tensor(u0))
+    del rho0, u0
+    t0 = forward - adjoint
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record(sim.stream)
+    done = 0
+    while done < t0:
+        k = min(500, t0 - done)
+        sim.step(k)
+        done += k
+        print(f"[bench] collision forward step {done}", file=sys.stderr, flush=True)
+    state = sim.get_state().clone()
+    sim.step(adjoint)
+    e[1].record(sim.stream)
+    rho_T = sim.fields()["rho"]
+    e[2].record(sim.stream)
+    sim.adjoint_seed(2.0 * (rho_T - r0))
+    del rho_T
+    print("[bench] collision adjoint", file=sys.stderr, flush=True)
+    stats = reverse_binomial(sim, state, t0, forward, snapshots)
+    e[3].record(sim.stream)
+    torch.cuda.synchronize()
+    fwd_ms = e[0].elapsed_time(e[1]) / forward
+    bwd_ms = e[2].elapsed_time(e[3])
+    adj_ms = (bwd_ms - stats["recompute_steps"] * fwd_ms) / adjoint
+    g = sim.adjoint_grads()
+    nodes = n ** 3
+    out = {"workload": "head-on collision 512^3 FP32, two r=64 droplets 160 apart at +-0.04, T=0.85Tc",
+           "forward_steps": forward, "adjoint_steps": adjoint, "snapshots": snapshots,
+           "recompute_steps": stats["recompute_steps"], "ms_per_forward_step": fwd_ms,
+           "mlups_forward": nodes / (fwd_ms / 1e3) / 1e6, "backward_s": bwd_ms / 1e3,
+           "ms_per_adjoint_step_excl_recompute": adj_ms, "mlups_adjoint": nodes / (adj_ms / 1e3) / 1e6,
+           "peak_device_GB": torch.cuda.max_memory_allocated() / 1e9, "dL_dkappa": g["kappa"]}
+    sim.close()
+    return out
+
+
 def cpu_baseline(rho, u, geom, seconds_target=20.0):
     """The CPU oracle as it stands, on the full-size workload for a bounded
     number of steps (about 10-30 s of CPU work)."""
@@ -241,6 +293,8 @@ def main():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--adjoint-only", action="store_true", help="time only the adjoint leg, print its JSON")
     ap.add_argument("--adjoint-steps", type=int, default=20)
+    ap.add_argument("--collision-adjoint", nargs=3, type=int, metavar=("FORWARD", "ADJOINT", "SNAPSHOTS"),
+                    help="time the 512^3 collision with a binomial-checkpointed adjoint of its last steps")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, form=args.forms.split(",")[0], workload_name=args.workload,
@@ -256,6 +310,9 @@ def main():
     if not torch.cuda.is_available():
         sys.stderr.write("bench.py needs a GPU\n")
         sys.exit(1)
+    if args.collision_adjoint:
+        print(json.dumps(time_collision_adjoint(lbfe, torch, *args.collision_adjoint)), flush=True)
+        return
     if args.adjoint_only:
         print(json.dumps(time_adjoint(lbfe, torch, steps=args.adjoint_steps)), flush=True)
         return

@@ -5,17 +5,19 @@
 runs `cfg.steps` time steps from the initial density rho0 (float64 tensor
 on the GPU, shape (nz, ny, nx)) and returns the final density field.  Its
 backward pass seeds lambda(T) = dL/drho_T, sweeps the adjoint steps in
-reverse, recomputing the forward states segment by segment from checkpoints
-taken every `cfg.checkpoint_every` steps (uniform checkpointing: memory is
-T/K checkpoints plus K states of one segment), and returns dL/drho0,
-dL/dkappa and dL/d(wet_value).  The recomputation is bitwise identical to
-the forward pass, so the gradients do not depend on K.
+reverse and returns dL/drho0, dL/dkappa and dL/d(wet_value).  The forward
+states are recomputed either segment by segment from checkpoints taken every
+`cfg.checkpoint_every` steps (uniform: memory is T/K checkpoints plus K
+states of one segment) or by the binomial schedule of reverse_binomial
+(memory: `cfg.snapshots` states).  The recomputation is bitwise identical to
+the forward pass, so the gradients do not depend on the schedule.
 
 kappa and wet_value are 0-d tensors; their values configure the library
 context (the HIP library needs them as parameters), their gradients come
 from the adjoint's accumulators.  All arithmetic runs in liblbfe.so.
 """
 from dataclasses import dataclass, field
+from math import comb
 
 import torch
 
@@ -39,12 +41,66 @@ class StepConfig:
     u0: object = None          # optional (3, nz, ny, nx) initial velocity
     device: str = "cuda"
     stats: dict = field(default_factory=dict)   # filled with timing/memory info
+    # "uniform": a checkpoint every checkpoint_every steps and the states of
+    # one segment held during its reversal; "binomial": at most `snapshots`
+    # stored states besides the initial one, placed by the binomial
+    # (revolve) schedule, for runs whose states do not all fit in memory
+    checkpoint: str = "uniform"
+    snapshots: int = 8
 
     def make(self, kappa, wet_value):
         return lbfe.Simulation(device=self.device, nx=self.nx, ny=self.ny, nz=self.nz, T=self.T, nu=self.nu,
                                kappa=float(kappa), walls_z=self.walls_z, wet_mode=self.wet_mode,
                                wet_value=float(wet_value), precision=self.precision, corr4=self.corr4,
                                omega=self.omega, adjoint=1, check_every=max(1, self.checkpoint_every))
+
+
+def reverse_binomial(sim, state_a, a, b, snapshots, stats=None):
+    """Run the adjoint steps b-1, ..., a (lambda(b) must be seeded) from the
+    stored state f(a), holding at most `snapshots` further states at once.
+    With t = b - a steps and s snapshots, r is the least number of forward
+    sweeps with C(s + r, s) >= t; the next snapshot is placed after m steps,
+    where the right part (t - m steps) is reversible with s - 1 snapshots and
+    r sweeps and the left part (m steps) with s snapshots and r - 1 sweeps
+    (C(s + r, s) = C(s - 1 + r, s - 1) + C(s + r - 1, s)).  Every recomputed
+    state is bitwise the one of the forward run, so the gradients do not
+    depend on the schedule."""
+    if stats is None:
+        stats = {}
+    stats.setdefault("recompute_steps", 0)
+    stats.setdefault("max_held", 0)
+
+    def rev(st, lo, hi, s, held):
+        stats["max_held"] = max(stats["max_held"], held)
+        t = hi - lo
+        if t == 1:
+            sim.adjoint_step(st)
+            return
+        if s == 0:  # no memory left: recompute from lo for every step
+            for k in range(hi - 1, lo - 1, -1):
+                if k == lo:
+                    sim.adjoint_step(st)
+                else:
+                    sim.set_state(st, lo)
+                    sim.step(k - lo)
+                    stats["recompute_steps"] += k - lo
+                    sim.adjoint_step(sim.get_state().clone())
+            return
+        r = 1
+        while comb(s + r, s) < t:
+            r += 1
+        m = min(t - 1, comb(s + r - 1, s))
+        m = max(m, t - comb(s - 1 + r, s - 1), 1)
+        sim.set_state(st, lo)
+        sim.step(m)
+        stats["recompute_steps"] += m
+        st_m = sim.get_state().clone()
+        rev(st_m, lo + m, hi, s - 1, held + 1)
+        del st_m
+        rev(st, lo, lo + m, s, held)
+
+    rev(state_a, a, b, int(snapshots), 0)
+    return stats
 
 
 class LBFEFunction(torch.autograd.Function):
@@ -54,9 +110,13 @@ class LBFEFunction(torch.autograd.Function):
         sim.init_density(rho0.detach(), cfg.u0)
         K = max(1, int(cfg.checkpoint_every))
         checkpoints = {}
-        for s in range(0, cfg.steps, K):
-            checkpoints[s] = sim.get_state().clone()
-            sim.step(min(K, cfg.steps - s))
+        if cfg.checkpoint == "binomial":
+            checkpoints[0] = sim.get_state().clone()
+            sim.step(cfg.steps)
+        else:
+            for s in range(0, cfg.steps, K):
+                checkpoints[s] = sim.get_state().clone()
+                sim.step(min(K, cfg.steps - s))
         rho_T = sim.fields()["rho"]
         ctx.sim, ctx.cfg, ctx.checkpoints = sim, cfg, checkpoints
         ctx.save_for_backward(rho0)
@@ -68,17 +128,20 @@ class LBFEFunction(torch.autograd.Function):
         (rho0,) = ctx.saved_tensors
         K = max(1, int(cfg.checkpoint_every))
         sim.adjoint_seed(grad_rho.detach().to(torch.float64))
-        starts = sorted(ctx.checkpoints, reverse=True)
-        for s0 in starts:
-            s1 = min(s0 + K, cfg.steps)
-            sim.set_state(ctx.checkpoints[s0], s0)
-            states = [sim.get_state().clone()]
-            for _ in range(s0 + 1, s1):
-                sim.step(1)
-                states.append(sim.get_state().clone())
-            for t in range(s1 - 1, s0 - 1, -1):
-                sim.adjoint_step(states[t - s0])
-            del states
+        if cfg.checkpoint == "binomial":
+            if cfg.steps > 0:
+                reverse_binomial(sim, ctx.checkpoints[0], 0, cfg.steps, cfg.snapshots, cfg.stats)
+        else:
+            for s0 in sorted(ctx.checkpoints, reverse=True):
+                s1 = min(s0 + K, cfg.steps)
+                sim.set_state(ctx.checkpoints[s0], s0)
+                states = [sim.get_state().clone()]
+                for _ in range(s0 + 1, s1):
+                    sim.step(1)
+                    states.append(sim.get_state().clone())
+                for t in range(s1 - 1, s0 - 1, -1):
+                    sim.adjoint_step(states[t - s0])
+                del states
         g_rho0 = sim.adjoint_init_density(rho0.detach(), cfg.u0)
         g = sim.adjoint_grads()
         dev = grad_rho.device

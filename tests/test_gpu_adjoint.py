@@ -158,11 +158,14 @@ def test_end_to_end_gradients_vs_oracle_and_fd(walls, wet_mode, wet_value):
 
 
 def test_checkpoint_interval_does_not_change_gradients():
+    """Uniform checkpoints every 1, 4, 9 steps and the binomial schedule with
+    two snapshots give bitwise identical gradients."""
     shape = (10, 8, 8)
     rho0, tgt, cfg = _loss_setup(shape, True, 1, 1.3, 9)
     grads = []
-    for K in (1, 4, 9):
-        cfg.checkpoint_every = K
+    for K, mode in ((1, "uniform"), (4, "uniform"), (9, "uniform"), (0, "binomial")):
+        cfg.checkpoint_every = max(K, 1)
+        cfg.checkpoint, cfg.snapshots = mode, 2
         r0 = torch.tensor(rho0, device="cuda", requires_grad=True)
         kap = torch.tensor(0.02, dtype=DT, requires_grad=True)
         wet = torch.tensor(1.3, dtype=DT, requires_grad=True)
