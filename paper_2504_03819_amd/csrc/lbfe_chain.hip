@@ -35,6 +35,7 @@ constexpr int WP = TX + 2, HP = TY + 2, NP = WP * HP;  // phi region (halo 1)
 constexpr int MR = (NR + CB - 1) / CB;         // rho points per thread
 constexpr int MM = (NM + CB - 1) / CB;         // mu points per thread
 constexpr int MP = (NP + CB - 1) / CB;         // phi points per thread
+constexpr int NRP = MR * CB;                   // rho plane in LDS, padded to whole rounds
 constexpr double A1 = 1.0 / 6.0, A0 = 2.0 / 3.0;       // D1Q3 weights
 
 // Branch-free global access: raw buffer loads/stores through a descriptor
@@ -79,7 +80,7 @@ template <int P>
 __global__ __launch_bounds__(CB) void k_chain(KP kp, const double *__restrict__ rho, const double *__restrict__ mu0,
                                               const void *jq, double *__restrict__ mu, void *Fq, void *Qq, int cz) {
     using real = typename Pol<P>::real;
-    __shared__ double sr[3][NR];
+    __shared__ double sr[3][NRP];
     __shared__ double sm[2][NM];
     __shared__ real sp[3][NP];
 
@@ -160,12 +161,13 @@ __global__ __launch_bounds__(CB) void k_chain(KP kp, const double *__restrict__ 
             for (int m = 0; m < MP; ++m) bload(pj[m][c], rj, offp[m]);
         }
     };
+    // every lane writes (the padding takes the lanes past the region, and a
+    // plane outside a walled box is written but never read), so the commit
+    // has no lane-divergent branch around the wait for its loads
     auto commit_rho = [&](int p) {
-        if (!valid(p)) return;
         const int s = slot3(p);
 #pragma unroll
-        for (int m = 0; m < MR; ++m)
-            if (tid + m * CB < NR) sr[s][tid + m * CB] = pr[m];
+        for (int m = 0; m < MR; ++m) sr[s][tid + m * CB] = pr[m];
     };
 
     // register rings, index 0/1/2 = planes p-1, p, p+1 of the consumer

@@ -36,12 +36,23 @@ template <int P> struct Pops;
 // i.e. element (i, z, y, x) sits at ((z ny + y) 27 + i) nx + x.  A wave of
 // 64 x-consecutive threads touches one contiguous run per population, and
 // the 27 runs of a row share DRAM pages.
+//
+// Population loads are non-temporal: every kernel reads a population once
+// per pass, and a lattice of a few hundred MB would otherwise push the
+// reused data (aux fields, stencil halos, the freshly written lattice) out
+// of the last-level cache.  Stores stay ordinary (non-temporal stores of the
+// shifted push-stream rows were measured slower).
+__device__ inline double ldnt(const double *p) { return __builtin_nontemporal_load(p); }
+__device__ inline float ldnt(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ inline __half ldnt(const __half *p) {
+    return __builtin_bit_cast(__half, __builtin_nontemporal_load((const unsigned short *)p));
+}
 template <> struct Pops<LBFE_FP64> {
     double *p;
     unsigned nx;
     __device__ Pops(const void *q, const KP &kp) : p((double *)q), nx((unsigned)kp.nx) {}
     __device__ size_t off(int i, unsigned row, unsigned x) const { return ((size_t)row * 27 + i) * nx + x; }
-    __device__ double ld(int i, unsigned row, unsigned x) const { return p[off(i, row, x)]; }
+    __device__ double ld(int i, unsigned row, unsigned x) const { return ldnt(p + off(i, row, x)); }
     __device__ void st(int i, unsigned row, unsigned x, double v) const { p[off(i, row, x)] = v; }
     __device__ static double quant(int, double v) { return v; }  // value a store then load returns
 };
@@ -51,7 +62,7 @@ template <> struct Pops<LBFE_FP32> {
     unsigned nx;
     __device__ Pops(const void *q, const KP &kp) : p((float *)q), nx((unsigned)kp.nx) {}
     __device__ size_t off(int i, unsigned row, unsigned x) const { return ((size_t)row * 27 + i) * nx + x; }
-    __device__ float ld(int i, unsigned row, unsigned x) const { return p[off(i, row, x)]; }
+    __device__ float ld(int i, unsigned row, unsigned x) const { return ldnt(p + off(i, row, x)); }
     __device__ void st(int i, unsigned row, unsigned x, float v) const { p[off(i, row, x)] = v; }
     __device__ static float quant(int, float v) { return v; }
 };
@@ -79,7 +90,7 @@ template <> struct Pops<LBFE_FP16_DEV> {
     unsigned nx;
     __device__ Pops(const void *q, const KP &kp) : p((__half *)q), nx((unsigned)kp.nx) {}
     __device__ size_t off(int i, unsigned row, unsigned x) const { return ((size_t)row * 27 + i) * nx + x; }
-    __device__ float ld(int i, unsigned row, unsigned x) const { return dec16(i, p[off(i, row, x)]); }
+    __device__ float ld(int i, unsigned row, unsigned x) const { return dec16(i, ldnt(p + off(i, row, x))); }
     __device__ void st(int i, unsigned row, unsigned x, float v) const { p[off(i, row, x)] = enc16(i, v); }
     __device__ static float quant(int i, float v) { return dec16(i, enc16(i, v)); }
 };
@@ -96,7 +107,7 @@ template <> struct Pops<LBFE_FP16_DEV_F0FP32> {
     __device__ static int slot(int i) { return i < kRest ? i : i - 1; }
     __device__ size_t off(int i, unsigned row, unsigned x) const { return ((size_t)row * 26 + slot(i)) * nx + x; }
     __device__ float ld(int i, unsigned row, unsigned x) const {
-        return i == kRest ? p0[(size_t)row * nx + x] : dec16(i, p[off(i, row, x)]);
+        return i == kRest ? ldnt(p0 + (size_t)row * nx + x) : dec16(i, ldnt(p + off(i, row, x)));
     }
     __device__ void st(int i, unsigned row, unsigned x, float v) const {
         if (i == kRest)
