@@ -4,7 +4,11 @@ Sec. II B) and the wetting boundary of Sec. III C.
 
 State layout: f has shape (27, nz, ny, nx), direction order from
 ``oracle.lattice``.  With walls, z = 0 and z = nz-1 are solid planes whose
-populations are kept at zero; all other nodes are fluid.
+populations are kept at zero; all other nodes are fluid.  An arbitrary solid
+voxel mask (``Params.solid``) generalises the planes: the halfway bounce-back
+and the wetting boundary of Eqs. (36)-(38) are written in the paper for any
+solid node x_s, and the flat walls are the case of a mask holding the two
+planes.
 
 Readings of points the paper leaves open (each also listed in the design
 notes of the repository):
@@ -59,6 +63,9 @@ class Params:
     # tangential velocities (ux, uy) of the bottom (z = 0) and top (z = nz-1)
     # walls; moving walls use the momentum-corrected halfway bounce-back
     wall_u: tuple = (0.0, 0.0, 0.0, 0.0)
+    # optional solid voxel mask, bool (nz, ny, nx), True = solid; combined
+    # with the wall planes when both are given
+    solid: object = None
 
     def coexistence(self):
         if self.rho_l > 0 and self.rho_v > 0:
@@ -98,24 +105,35 @@ def lap_h(g):
     return out
 
 
+def has_solid(p: Params):
+    return bool(p.walls_z) or p.solid is not None
+
+
 def fluid_mask(p: Params):
+    """Fluid indicator s (1 fluid, 0 solid) of the wall planes and the
+    solid mask."""
     s = torch.ones((p.nz, p.ny, p.nx), dtype=DT)
     if p.walls_z:
         s[0] = 0.0
         s[-1] = 0.0
+    if p.solid is not None:
+        s = torch.where(torch.as_tensor(p.solid, dtype=torch.bool), torch.zeros_like(s), s)
     return s
 
 
 def wall_average(g, s):
     """Eqs. (36)/(37): sum_i w_i s_w g(x+c_i) / sum_i w_i s_w, evaluated at
-    every node (only used at solid nodes).  s is the fluid indicator."""
+    every node (only used at solid nodes).  s is the fluid indicator; values
+    of g at non-fluid nodes never enter.  A solid node without fluid
+    neighbours (inside a thick solid) gets 0: no stencil of a fluid node
+    reaches it."""
     num = torch.zeros_like(g)
     den = torch.zeros_like(g)
     for i, c in enumerate(C):
-        sw = at(s, c)
-        num = num + W_T[i] * sw * at(g, c)
-        den = den + W_T[i] * sw
-    return num / den
+        fl = at(s, c) > 0
+        num = num + torch.where(fl, W_T[i] * at(g, c), torch.zeros_like(g))
+        den = den + torch.where(fl, torch.full_like(g, W_T[i]), torch.zeros_like(g))
+    return torch.where(den > 0, num / torch.where(den > 0, den, torch.ones_like(den)), torch.zeros_like(g))
 
 
 # --------------------------------------------------------------------------
@@ -278,7 +296,7 @@ def wall_density(rho_f, s, p: Params):
     solid nodes filled in."""
     rl, rv = p.coexistence()
     lo, hi = 0.05 * rl + 0.95 * rv, 0.95 * rl + 0.05 * rv
-    rave = wall_average(rho_f * s, s)
+    rave = wall_average(rho_f, s)
     inwin = (rave >= lo) & (rave <= hi)
     if p.wet_mode == PHI:
         mod = torch.clamp(p.wet_value * rave, lo, hi)
@@ -298,12 +316,15 @@ def aux_fields(f, p: Params):
     fluid = s > 0
     rho_f = f.sum(0)
     j = torch.einsum("ia,i...->a...", torch.tensor(C, dtype=DT), f)
-    # S2: density at solid nodes (flat walls only when walls_z)
-    rho = wall_density(rho_f, s, p) if p.walls_z else rho_f
-    # S3: chemical potential, Eq. (32), then Eq. (36) at solid nodes
-    mu = mu_bulk(rho, p) - p.kappa * lap_h(rho)
-    if p.walls_z:
-        mu = torch.where(fluid, mu, wall_average(mu * s, s))
+    # S2: density at solid nodes
+    rho = wall_density(rho_f, s, p) if has_solid(p) else rho_f
+    # S3: chemical potential, Eq. (32), then Eq. (36) at solid nodes (a
+    # solid node inside a thick solid keeps rho = 0; mu0 is taken at a
+    # harmless density there and never used)
+    rho_m = torch.where(fluid, rho, torch.where(rho > 0, rho, torch.ones_like(rho)))
+    mu = mu_bulk(rho_m, p) - p.kappa * lap_h(rho)
+    if has_solid(p):
+        mu = torch.where(fluid, mu, wall_average(mu, s))
     # S4: Eq. (11)-(12)
     pm = (1.0 + mu) / 3.0
     G = grad_h(mu)
@@ -341,6 +362,8 @@ def stream(fs, p: Params, rho=None, pm=None):
     in u_w, the familiar 2 w_o rho c_o . u_w / c_s^2."""
     s = fluid_mask(p)
     moving = p.walls_z and any(v != 0.0 for v in p.wall_u)
+    if moving and p.solid is not None:
+        raise ValueError("moving walls are defined for the wall planes only")
     if moving:
         shape = tuple(fs.shape[1:])
 
@@ -355,7 +378,7 @@ def stream(fs, p: Params, rho=None, pm=None):
     out = []
     for i, c in enumerate(C):
         pulled = at(fs[i], (-c[0], -c[1], -c[2]))
-        if p.walls_z:
+        if has_solid(p):
             src_fluid = at(s, (-c[0], -c[1], -c[2])) > 0
             back = fs[OPP[i]]
             if moving and c[2] != 0:
@@ -385,9 +408,11 @@ def init(rho0, p: Params, u0=None):
     """Initial populations: Eq. (20) equilibrium CMs at (rho0, u0, p_m) with
     p_m from mu[rho0] (wall densities from Eqs. (37)-(38) first)."""
     s = fluid_mask(p)
+    fluid = s > 0
     rho0 = rho0.to(DT)
-    rho = wall_density(rho0, s, p) if p.walls_z else rho0
-    mu = mu_bulk(rho, p) - p.kappa * lap_h(rho)
+    rho = wall_density(rho0, s, p) if has_solid(p) else rho0
+    rho_m = torch.where(fluid, rho, torch.where(rho > 0, rho, torch.ones_like(rho)))
+    mu = mu_bulk(rho_m, p) - p.kappa * lap_h(rho)
     pm = (1.0 + mu) / 3.0
     if u0 is None:
         u0 = torch.zeros((3,) + tuple(rho0.shape), dtype=DT)

@@ -104,3 +104,46 @@ def perturb_populations(f, amplitude, seed):
     """Add seeded uniform noise to a (27, ...) population array (used to
     leave the equilibrium manifold in parity checks)."""
     return f + uniform_noise(f.shape, amplitude, seed)
+
+
+# ---------------------------------------------------------------------------
+# solid voxel masks (uint8, 1 = solid, shape (nz, ny, nx))
+# ---------------------------------------------------------------------------
+def mask_planes(shape):
+    """The two flat walls z = 0 and z = nz-1 as a mask."""
+    m = np.zeros(shape, dtype=np.uint8)
+    m[0] = 1
+    m[-1] = 1
+    return m
+
+
+def mask_obstacles(shape, seed=11):
+    """A periodic box with assorted solids: a ball, a pillar through the
+    whole height, a thick block (with solid nodes that touch no fluid) and a
+    few seeded single voxels.  Sizes scale with the box; at least 8^3."""
+    nz, ny, nx = shape
+    z, y, x = _grid(shape)
+    m = np.zeros(shape, dtype=np.uint8)
+    r = max(1.5, min(shape) / 6.0)
+    m[(x - 0.3 * nx) ** 2 + (y - 0.35 * ny) ** 2 + (z - 0.4 * nz) ** 2 <= r * r] = 1
+    m[:, int(0.7 * ny):int(0.7 * ny) + 2, int(0.75 * nx) % nx] = 1
+    bz, by, bx = max(3, nz // 4), max(3, ny // 4), max(3, nx // 4)
+    m[nz - bz:, :by, nx - bx:] = 1
+    g = np.random.Generator(np.random.PCG64(seed))
+    for _ in range(3):
+        m[g.integers(nz), g.integers(ny), g.integers(nx)] = 1
+    return m
+
+
+def mask_pillars(shape, plate=2, pitch=12, width=4, height=6):
+    """A patterned substrate: a solid plate of `plate` layers at the bottom,
+    square pillars of `width` x `width` and `height` layers on a square
+    lattice of `pitch`, and a flat solid top layer."""
+    nz, ny, nx = shape
+    m = np.zeros(shape, dtype=np.uint8)
+    m[:plate] = 1
+    m[-1] = 1
+    z, y, x = _grid(shape)
+    pill = ((x % pitch) < width) & ((y % pitch) < width) & (z < plate + height)
+    m[np.broadcast_to(pill, shape)] = 1
+    return m
