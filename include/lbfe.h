@@ -92,6 +92,9 @@ typedef struct lbfe_params {
                             test of Sec. III B: momentum-corrected halfway
                             bounce-back; |u| <= 0.3; nonzero needs
                             walls_z = 1 and adjoint = 0; 0 = resting walls */
+    int32_t solid_mask;  /* 1: the solid nodes come from a voxel mask given
+                            by lbfe_set_solid (needs walls_z = 0, adjoint =
+                            0, resting walls); 0: none or the wall planes */
 } lbfe_params;
 
 typedef struct lbfe_ctx lbfe_ctx;
@@ -125,6 +128,20 @@ int lbfe_bind_workspace(lbfe_ctx *ctx, void *workspace_dev, size_t bytes);
 
 /* Copy the context's parameters, with derived rho_l/rho_v, into *out. */
 int lbfe_get_params(const lbfe_ctx *ctx, lbfe_params *out);
+
+/* Solid voxel mask (params.solid_mask = 1): the halfway bounce-back of
+ * Eq. (10) and the wetting boundary of Eqs. (36)-(38) at every solid node
+ * x_s, which Sec. III C writes for a general x_s (curved or patterned
+ * substrates; flat walls are the mask of the planes z = 0 and z = nz-1).
+ * mask_dev: device uint8[nz][ny][nx], nonzero = solid, read during the call
+ * (the library keeps its own per-node neighbour words; the caller may free
+ * the mask afterwards).  Periodic wrap at the box faces.  Solid nodes hold
+ * no populations; their rho is the wetting density (0 if no fluid
+ * neighbour), their u, F, Q are 0.  Discards the state: call
+ * lbfe_init_density (or lbfe_set_state / lbfe_set_populations) after it.
+ * E_STATE if the context was created with solid_mask = 0 or has no
+ * workspace; E_INVAL for a null mask. */
+int lbfe_set_solid(lbfe_ctx *ctx, const uint8_t *mask_dev);
 
 /* Initial state (Sec. III B, Eqs. (34)-(35) give the paper's droplets):
  * populations at the generalized equilibrium of Eq. (20) with density rho0,

@@ -8,7 +8,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "liblbfe.so")
-SOURCES = ["lbfe_api.hip", "lbfe_kernels.hip", "lbfe_chain.hip", "lbfe_fused.hip", "lbfe_adjoint.hip"]
+SOURCES = ["lbfe_api.hip", "lbfe_kernels.hip", "lbfe_chain.hip", "lbfe_fused.hip", "lbfe_mask.hip",
+           "lbfe_adjoint.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

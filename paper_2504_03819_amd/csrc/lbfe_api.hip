@@ -27,6 +27,7 @@ struct lbfe_ctx {
     bool bound = false, initialised = false, adj_seeded = false;
     bool fused = false;   // fused collide-stream-moments step (LBFE_FUSED=1)
     bool aux_ok = false;  // rho, j, mu0 hold the moments of f[cur]
+    bool mask_set = false;  // a solid mask has been given (solid_mask = 1)
     std::string err;
 };
 
@@ -116,12 +117,15 @@ std::string validate(const lbfe_params &p) {
     }
     if (moving && !p.walls_z) return "moving walls need walls_z = 1";
     if (moving && p.adjoint) return "the adjoint does not cover moving walls";
+    if (p.solid_mask != 0 && p.solid_mask != 1) return "solid_mask must be 0 or 1";
+    if (p.solid_mask && p.walls_z) return "solid_mask replaces walls_z (put the planes into the mask)";
+    if (p.solid_mask && p.adjoint) return "the adjoint does not cover solid masks";
     return "";
 }
 
 // Workspace layout: every sub-buffer 256-byte aligned.
 struct Layout {
-    size_t f0, f1, rho, j, mu, mu0, F, Q, flag, part, red, lam0, lam1, abuf, agrad, total;
+    size_t f0, f1, rho, j, mu, mu0, F, Q, nbr, phi, flag, part, red, lam0, lam1, abuf, agrad, total;
 };
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -141,6 +145,10 @@ Layout layout(const lbfe_params &p) {
     L.mu0 = take(8 * N);
     L.F = take(3 * rb * N);
     L.Q = take(3 * rb * N);
+    if (p.solid_mask) {
+        L.nbr = take(4 * N);
+        L.phi = take(3 * rb * N);
+    }
     L.flag = take(256);
     L.part = take(8 * 8 * (size_t)nblocks(nf) + 8 * 8 * (size_t)nblocks(N));
     L.red = take(64);
@@ -158,6 +166,14 @@ int need_bound(lbfe_ctx *c) {
     if (!c) return LBFE_E_INVAL;
     if (!c->bound) return fail(c, LBFE_E_STATE, "no workspace bound (lbfe_bind_workspace)");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, LBFE_E_DEVICE, "hipSetDevice failed");
+    return LBFE_OK;
+}
+
+// a context with solid_mask = 1 needs its mask before any state
+int need_mask(lbfe_ctx *c) {
+    int r = need_bound(c);
+    if (r) return r;
+    if (c->p.solid_mask && !c->mask_set) return fail(c, LBFE_E_STATE, "no solid mask (lbfe_set_solid)");
     return LBFE_OK;
 }
 
@@ -234,7 +250,7 @@ int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out) {
         if (q.T > 0.3 * Tc && q.T < Tc && maxwell_pair(Vdw{q.a, q.b, q.R, q.T}, rl, rv)) {
             q.rho_l = rl;
             q.rho_v = rv;
-        } else if (q.walls_z && q.wet_mode != LBFE_WET_NEUTRAL) {
+        } else if ((q.walls_z || q.solid_mask) && q.wet_mode != LBFE_WET_NEUTRAL) {
             std::fprintf(stderr, "lbfe_create: no coexistence pair at this T; give rho_l, rho_v\n");
             return LBFE_E_INVAL;
         }
@@ -268,6 +284,7 @@ int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out) {
     k.corr4 = q.corr4;
     for (int i = 0; i < 4; ++i) k.wall_u[i] = q.wall_u[i];
     k.moving = q.wall_u[0] != 0.0 || q.wall_u[1] != 0.0 || q.wall_u[2] != 0.0 || q.wall_u[3] != 0.0;
+    k.masked = q.solid_mask;
     k.wet_mode = q.wet_mode;
     k.wet_value = q.wet_value;
     k.lo = 0.05 * q.rho_l + 0.95 * q.rho_v;
@@ -284,7 +301,7 @@ int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out) {
     // SIMD; measured on gfx950 it is on par in FP64 and slower in the FP32
     // and FP16 forms.
     const char *fu = std::getenv("LBFE_FUSED");
-    c->fused = fu && fu[0] == '1' && !k.moving;  // the fused kernel has resting walls only
+    c->fused = fu && fu[0] == '1' && !k.moving && !k.masked;  // resting walls, no mask
     *out = c;
     return LBFE_OK;
 }
@@ -307,6 +324,10 @@ int lbfe_bind_workspace(lbfe_ctx *c, void *ws, size_t bytes) {
     c->b.mu0 = (double *)(w + L.mu0);
     c->b.F = w + L.F;
     c->b.Q = w + L.Q;
+    if (c->p.solid_mask) {
+        c->b.nbr = (unsigned *)(w + L.nbr);
+        c->b.phi = w + L.phi;
+    }
     c->b.flag = (int *)(w + L.flag);
     c->b.part = (double *)(w + L.part);
     c->b.red = (double *)(w + L.red);
@@ -321,6 +342,7 @@ int lbfe_bind_workspace(lbfe_ctx *c, void *ws, size_t bytes) {
     c->bound = true;
     c->initialised = false;
     c->aux_ok = false;
+    c->mask_set = false;
     c->adj_seeded = false;
     c->cur = 0;
     c->step = 0;
@@ -333,12 +355,27 @@ int lbfe_get_params(const lbfe_ctx *c, lbfe_params *out) {
     return LBFE_OK;
 }
 
-int lbfe_init_density(lbfe_ctx *c, const double *rho0, const double *u0) {
+int lbfe_set_solid(lbfe_ctx *c, const uint8_t *mask) {
     int r = need_bound(c);
+    if (r) return r;
+    if (!c->p.solid_mask) return fail(c, LBFE_E_STATE, "created with solid_mask = 0");
+    if (!mask) return fail(c, LBFE_E_INVAL, "null mask");
+    hipError_t e = launch_mask_prep(c->stream, c->kp, c->b, mask);
+    if (e != hipSuccess) return hip_fail(c, e, "set_solid");
+    c->mask_set = true;
+    c->initialised = false;
+    c->aux_ok = false;
+    return LBFE_OK;
+}
+
+int lbfe_init_density(lbfe_ctx *c, const double *rho0, const double *u0) {
+    int r = need_mask(c);
     if (r) return r;
     if (!rho0) return fail(c, LBFE_E_INVAL, "rho0 is null");
     hipError_t e = launch_fill(c->stream, c->b.flag, 256);
-    if (e == hipSuccess) e = launch_check_rho0(c->stream, c->kp, rho0, c->b.flag);
+    if (e == hipSuccess)
+        e = c->kp.masked ? launch_check_rho0_mask(c->stream, c->kp, c->b, rho0, c->b.flag)
+                         : launch_check_rho0(c->stream, c->kp, rho0, c->b.flag);
     if (e != hipSuccess) return hip_fail(c, e, "init check");
     int flag = 0;
     if ((r = read_flag(c, flag))) return r;
@@ -459,7 +496,7 @@ int lbfe_get_state(lbfe_ctx *c, void *dst) {
 }
 
 int lbfe_set_state(lbfe_ctx *c, const void *src, int64_t step) {
-    int r = need_bound(c);
+    int r = need_mask(c);
     if (r) return r;
     if (!src) return fail(c, LBFE_E_INVAL, "null source");
     if (step < 0) return fail(c, LBFE_E_INVAL, "step < 0");
@@ -476,16 +513,16 @@ int lbfe_get_populations(lbfe_ctx *c, double *f) {
     int r = need_init(c);
     if (r) return r;
     if (!f) return fail(c, LBFE_E_INVAL, "null destination");
-    hipError_t e = launch_get_pop(c->stream, c->p.precision, c->kp, c->b.f[c->cur], f);
+    hipError_t e = launch_get_pop(c->stream, c->p.precision, c->kp, c->b, c->b.f[c->cur], f);
     if (e != hipSuccess) return hip_fail(c, e, "get_populations");
     return LBFE_OK;
 }
 
 int lbfe_set_populations(lbfe_ctx *c, const double *f) {
-    int r = need_bound(c);
+    int r = need_mask(c);
     if (r) return r;
     if (!f) return fail(c, LBFE_E_INVAL, "null source");
-    hipError_t e = launch_set_pop(c->stream, c->p.precision, c->kp, c->b.f[c->cur], f);
+    hipError_t e = launch_set_pop(c->stream, c->p.precision, c->kp, c->b, c->b.f[c->cur], f);
     if (e != hipSuccess) return hip_fail(c, e, "set_populations");
     c->aux_ok = false;
     c->initialised = true;

@@ -29,6 +29,7 @@ struct KP {
     int xcd_remap;             // map consecutive tiles onto one XCD
     double wall_u[4];          // (ux, uy) of the bottom and top walls
     int moving;                // some wall velocity is nonzero
+    int masked;                // solid voxel mask (Bufs::nbr) instead of planes
 };
 
 // Device pointers of one context (all inside the caller's workspace).
@@ -40,6 +41,8 @@ struct Bufs {
     double *mu0;         // [N] bulk part mu0(rho) of mu at fluid nodes
     void *F;             // [3][N] force, compute precision
     void *Q;             // [3][N] Q200, Q020, Q002 of Eq. (27), compute precision, 0 at solid
+    unsigned *nbr;       // [N] with a solid mask: bit i set when x + c_i is solid
+    void *phi;           // [3][N] phi of Eq. (27) (mask path), compute precision
     int *flag;           // divergence / domain flag
     double *part;        // reduction partials [nblk][8]
     double *red;         // final reductions [8]
@@ -65,11 +68,20 @@ hipError_t launch_fused(hipStream_t s, int prec, const KP &kp, const Bufs &b, in
 hipError_t launch_chain(hipStream_t s, int prec, const KP &kp, const Bufs &b);
 hipError_t launch_export(hipStream_t s, int prec, const KP &kp, const Bufs &b, int which, double *out);
 hipError_t launch_reduce(hipStream_t s, int prec, const KP &kp, const Bufs &b);
-hipError_t launch_get_pop(hipStream_t s, int prec, const KP &kp, const void *f, double *out);
-hipError_t launch_set_pop(hipStream_t s, int prec, const KP &kp, void *f, const double *in);
+hipError_t launch_get_pop(hipStream_t s, int prec, const KP &kp, const Bufs &b, const void *f, double *out);
+hipError_t launch_set_pop(hipStream_t s, int prec, const KP &kp, const Bufs &b, void *f, const double *in);
 hipError_t launch_check_rho0(hipStream_t s, const KP &kp, const double *rho0, int *flag);
 // rho0 (fluid nodes) -> rho with wall densities -> mu, as in the initialiser
 hipError_t launch_init_aux(hipStream_t s, const KP &kp, const Bufs &b, const double *rho0);
+
+// solid voxel masks (lbfe_mask.hip): neighbour words from a uint8 mask, and
+// the mask path's aux fields, step, initialiser and rho0 check
+hipError_t launch_mask_prep(hipStream_t s, const KP &kp, const Bufs &b, const uint8_t *solid);
+hipError_t launch_aux_mask(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur);
+hipError_t launch_step_mask(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, hipEvent_t *ev5);
+hipError_t launch_init_mask(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, const double *rho0,
+                            const double *u0);
+hipError_t launch_check_rho0_mask(hipStream_t s, const KP &kp, const Bufs &b, const double *rho0, int *flag);
 
 // adjoint (lbfe_adjoint.hip)
 size_t adjoint_aux_bytes(int prec, size_t N);

@@ -229,13 +229,13 @@ __global__ __launch_bounds__(kBlock) void k_check_rho(KP kp, const double *rho, 
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_export(KP kp, int which, const double *rho, const void *jq,
                                                    const double *mu, const void *Fq, const void *Qq,
-                                                   double *out) {
+                                                   const unsigned *nbr, double *out) {
     using real = real_t<P>;
     const unsigned n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= kp.N) return;
     int x, y, z;
     decompose(kp, n, x, y, z);
-    const bool fluid = z >= kp.z0 && z < kp.z1;
+    const bool fluid = kp.masked ? !(nbr[n] & (1u << kRest)) : (z >= kp.z0 && z < kp.z1);
     const size_t N = kp.N;
     const real *F = (const real *)Fq;
     switch (which) {
@@ -265,12 +265,12 @@ __global__ __launch_bounds__(kBlock) void k_export(KP kp, int which, const doubl
 // block partials in a fixed order.
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_reduce_part(KP kp, const double *rho, const void *jq, const void *Fq,
-                                                        double *part) {
+                                                        const unsigned *nbr, double *part) {
     using real = real_t<P>;
     __shared__ double s[8][kBlock];
     const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
     double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (idx < kp.nfluid) {
+    if (idx < kp.nfluid && !(kp.masked && (nbr[(unsigned)kp.z0 * kp.plane + idx] & (1u << kRest)))) {
         const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
         const size_t N = kp.N;
         const real *j = (const real *)jq, *F = (const real *)Fq;
@@ -317,11 +317,11 @@ __global__ __launch_bounds__(kBlock) void k_reduce_final(unsigned nblk, const do
 }
 
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_get_pop(KP kp, const void *fq, double *out) {
+__global__ __launch_bounds__(kBlock) void k_get_pop(KP kp, const void *fq, const unsigned *nbr, double *out) {
     const unsigned n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= kp.N) return;
     const unsigned z = n / kp.plane;
-    const bool fluid = (int)z >= kp.z0 && (int)z < kp.z1;
+    const bool fluid = kp.masked ? !(nbr[n] & (1u << kRest)) : ((int)z >= kp.z0 && (int)z < kp.z1);
     const Pops<P> f(fq, kp);
     const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
 #pragma unroll
@@ -329,14 +329,15 @@ __global__ __launch_bounds__(kBlock) void k_get_pop(KP kp, const void *fq, doubl
 }
 
 template <int P>
-__global__ __launch_bounds__(kBlock) void k_set_pop(KP kp, void *fq, const double *in) {
+__global__ __launch_bounds__(kBlock) void k_set_pop(KP kp, void *fq, const unsigned *nbr, const double *in) {
     const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
     if (idx >= kp.nfluid) return;
     const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
+    const bool solid = kp.masked && (nbr[n] & (1u << kRest));  // solid nodes hold no populations
     const Pops<P> f(fq, kp);
     const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
 #pragma unroll
-    for (int i = 0; i < 27; ++i) f.st(i, row, x, (real_t<P>)in[(size_t)i * kp.N + n]);
+    for (int i = 0; i < 27; ++i) f.st(i, row, x, solid ? (real_t<P>)0 : (real_t<P>)in[(size_t)i * kp.N + n]);
 }
 
 // --------------------------------------------------------------------------
@@ -417,15 +418,18 @@ hipError_t launch_fill(hipStream_t s, void *p, size_t bytes) {
 
 hipError_t launch_init(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, const double *rho0,
                        const double *u0) {
+    if (kp.masked) return launch_init_mask(s, prec, kp, b, cur, rho0, u0);
     return dispatch(prec, [&](auto pc) { return init_impl<decltype(pc)::value>(s, kp, b, cur, rho0, u0); });
 }
 
 hipError_t launch_aux(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur) {
+    if (kp.masked) return launch_aux_mask(s, prec, kp, b, cur);
     return dispatch(prec, [&](auto pc) { return aux_impl<decltype(pc)::value>(s, kp, b, cur); });
 }
 
 hipError_t launch_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, bool fused, bool refresh,
                        hipEvent_t *ev5) {
+    if (kp.masked) return launch_step_mask(s, prec, kp, b, cur, ev5);
     return dispatch(prec,
                     [&](auto pc) { return step_impl<decltype(pc)::value>(s, kp, b, cur, fused, refresh, ev5); });
 }
@@ -433,7 +437,7 @@ hipError_t launch_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int
 hipError_t launch_export(hipStream_t s, int prec, const KP &kp, const Bufs &b, int which, double *out) {
     return dispatch(prec, [&](auto pc) {
         constexpr int P = decltype(pc)::value;
-        k_export<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, which, b.rho, b.j, b.mu, b.F, b.Q, out);
+        k_export<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, which, b.rho, b.j, b.mu, b.F, b.Q, b.nbr, out);
         return hipGetLastError();
     });
 }
@@ -442,24 +446,24 @@ hipError_t launch_reduce(hipStream_t s, int prec, const KP &kp, const Bufs &b) {
     const unsigned g = nblocks(kp.nfluid);
     return dispatch(prec, [&](auto pc) {
         constexpr int P = decltype(pc)::value;
-        k_reduce_part<P><<<g, kBlock, 0, s>>>(kp, b.rho, b.j, b.F, b.part);
+        k_reduce_part<P><<<g, kBlock, 0, s>>>(kp, b.rho, b.j, b.F, b.nbr, b.part);
         k_reduce_final<<<1, kBlock, 0, s>>>(g, b.part, b.red);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_get_pop(hipStream_t s, int prec, const KP &kp, const void *f, double *out) {
+hipError_t launch_get_pop(hipStream_t s, int prec, const KP &kp, const Bufs &b, const void *f, double *out) {
     return dispatch(prec, [&](auto pc) {
         constexpr int P = decltype(pc)::value;
-        k_get_pop<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, f, out);
+        k_get_pop<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, f, b.nbr, out);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_set_pop(hipStream_t s, int prec, const KP &kp, void *f, const double *in) {
+hipError_t launch_set_pop(hipStream_t s, int prec, const KP &kp, const Bufs &b, void *f, const double *in) {
     return dispatch(prec, [&](auto pc) {
         constexpr int P = decltype(pc)::value;
-        k_set_pop<P><<<nblocks(kp.nfluid), kBlock, 0, s>>>(kp, f, in);
+        k_set_pop<P><<<nblocks(kp.nfluid), kBlock, 0, s>>>(kp, f, b.nbr, in);
         return hipGetLastError();
     });
 }

@@ -36,6 +36,7 @@ class Params(ctypes.Structure):
         ("rho_l", c_double), ("rho_v", c_double),
         ("check_every", c_int32), ("adjoint", c_int32),
         ("wall_u", c_double * 4),
+        ("solid_mask", c_int32),
     ]
 
 
@@ -59,6 +60,7 @@ def lib():
         "lbfe_workspace_bytes": (c_int, [P, POINTER(c_size_t)]),
         "lbfe_bind_workspace": (c_int, [V, V, c_size_t]),
         "lbfe_get_params": (c_int, [V, P]),
+        "lbfe_set_solid": (c_int, [V, V]),
         "lbfe_init_density": (c_int, [V, V, V]),
         "lbfe_step": (c_int, [V, c_int64]),
         "lbfe_step_count": (c_int, [V, POINTER(c_int64)]),
@@ -122,9 +124,13 @@ class Simulation:
     All calls are enqueued on the torch stream that is current at
     construction; tensors passed in must live on the same device."""
 
-    def __init__(self, params=None, device="cuda", **kw):
+    def __init__(self, params=None, device="cuda", solid=None, **kw):
+        """solid: optional (nz, ny, nx) mask (nonzero = solid voxel), which
+        sets params.solid_mask and is handed to lbfe_set_solid."""
         import torch
         self._torch = torch
+        if solid is not None:
+            kw["solid_mask"] = 1
         self.params = params if params is not None else default_params(**kw)
         if params is not None and kw:
             raise ValueError("give params or keyword overrides, not both")
@@ -147,6 +153,14 @@ class Simulation:
         self._check(L.lbfe_get_params(self._ctx, byref(q)))
         self.params = q
         self.shape = (int(q.nz), int(q.ny), int(q.nx))
+        if solid is not None:
+            self.set_solid(solid)
+
+    def set_solid(self, mask):
+        """Give the solid voxel mask (nonzero = solid); discards the state."""
+        m = self._dev(self._torch.as_tensor(mask) != 0, dtype=self._torch.uint8)
+        self._check(lib().lbfe_set_solid(self._ctx, _ptr(m)))
+        self.solid = m
 
     # -------------------------------------------------------------- utils --
     def _check(self, rc):

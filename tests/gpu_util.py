@@ -27,10 +27,12 @@ def rel_err(gpu, ora):
 
 def oracle_params(sim_or_params):
     p = sim_or_params.params if hasattr(sim_or_params, "params") else sim_or_params
+    solid = getattr(sim_or_params, "solid", None)
     return lbm.Params(int(p.nx), int(p.ny), int(p.nz), walls_z=bool(p.walls_z), a=p.a, b=p.b, R=p.R, T=p.T,
                       kappa=p.kappa, nu=p.nu, omega=list(p.omega), corr4=bool(p.corr4), rho_l=p.rho_l,
                       rho_v=p.rho_v, wet_mode=int(p.wet_mode), wet_value=p.wet_value,
-                      wall_u=tuple(float(v) for v in p.wall_u))
+                      wall_u=tuple(float(v) for v in p.wall_u),
+                      solid=None if solid is None else solid.cpu() != 0)
 
 
 def make_sim(**kw):

@@ -70,6 +70,7 @@ def test_coexistence_matches_oracle_maxwell():
     dict(nx=2048, ny=2048, nz=1024), dict(nx=32768, ny=16384, nz=1),
     dict(wall_u=(0.1, 0.0, 0.0, 0.0)), dict(walls_z=1, wall_u=(0.0, 0.0, 0.31, 0.0)),
     dict(walls_z=1, adjoint=1, wall_u=(0.1, 0.0, 0.1, 0.0)), dict(walls_z=1, wall_u=(float("nan"), 0.0, 0.0, 0.0)),
+    dict(solid_mask=2), dict(solid_mask=1, walls_z=1), dict(solid_mask=1, adjoint=1),
 ])
 def test_invalid_parameters_rejected_before_device(override):
     p = lbfe.default_params()
@@ -80,6 +81,19 @@ def test_invalid_parameters_rejected_before_device(override):
     assert ctx.value is None
     n = ctypes.c_size_t()
     assert lbfe.lib().lbfe_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == lbfe.E_INVAL
+
+
+def test_solid_mask_workspace_holds_neighbour_words_and_phi():
+    """A mask context adds one 32-bit neighbour word and three phi values
+    (compute precision) per node to the workspace."""
+    for prec, rb in ((lbfe.PRECISIONS["fp64"], 8), (lbfe.PRECISIONS["fp32"], 4)):
+        p = lbfe.default_params(nx=40, ny=30, nz=20, precision=prec)
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        assert lbfe.lib().lbfe_workspace_bytes(ctypes.byref(p), ctypes.byref(a)) == lbfe.OK
+        p.solid_mask = 1
+        assert lbfe.lib().lbfe_workspace_bytes(ctypes.byref(p), ctypes.byref(b)) == lbfe.OK
+        N = 40 * 30 * 20
+        assert b.value - a.value >= (4 + 3 * rb) * N and b.value - a.value < (4 + 3 * rb) * N + 1024
 
 
 def test_omega_range_checked_but_omega1_ignored():
