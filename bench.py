@@ -80,12 +80,25 @@ def workload(name, lbfe, torch):
         rho = inputs.sphere((128, 128, 128), (64, 64, 64), 30.0, rl, rv)
         desc = "droplet 128^3 r=30 between walls moving at U=0.1 (x), T=0.8Tc"
         return dict(nx=128, ny=128, nz=128, T=T, walls_z=1, wall_u=(0.1, 0.0, 0.1, 0.0)), rho, None, desc
+    if name == "pillars":
+        T = 0.7 * 8 * (9 / 392) / (27 * (2 / 21))
+        rl, rv = lbfe.coexistence(9 / 392, 2 / 21, 1.0, T)
+        shape = (96, 192, 192)
+        mask = inputs.mask_pillars(shape, plate=2, pitch=12, width=4, height=6)
+        rho = inputs.sphere(shape, (96.0, 96.0, 8.0), 32.0, rl, rv)
+        rho[mask.astype(bool)] = rv
+        desc = ("droplet r=32 on a pillared substrate 192x192x96 (solid mask: plate 2, pillars 4x4x6 at pitch 12, "
+                "solid top layer), drho=0.9, T=0.7Tc, omega3=0.5")
+        return dict(nx=192, ny=192, nz=96, T=T, wet_mode=2, wet_value=0.9, solid=mask,
+                    omega=[1.0, 1.0, 1.0, 0.5] + [1.0] * 7), rho, None, desc
     raise SystemExit(f"unknown workload {name}")
 
 
 def time_form(lbfe, torch, geom, rho, u, form, steps, warmup, timed_steps):
     sim = lbfe.Simulation(device="cuda:0", precision=form, **geom)
     nfluid = sim.params.nx * sim.params.ny * (sim.params.nz - (2 if sim.params.walls_z else 0))
+    if geom.get("solid") is not None:
+        nfluid = int((geom["solid"] == 0).sum())
     sim.init_density(torch.tensor(rho), None if u is None else torch.tensor(u))
     sim.step(warmup)
     torch.cuda.synchronize()
