@@ -49,7 +49,10 @@ __global__ __launch_bounds__(kBlock) void k_moments_m(KP kp, const unsigned *nbr
                                                       void *jq, int *flag) {
     using real = real_t<P>;
     const unsigned n = blockIdx.x * kBlock + threadIdx.x;
-    if (n >= kp.N || solid_at(nbr[n])) return;
+    if (n >= kp.N) return;
+    // the population loads do not wait for the neighbour word (a solid
+    // node's slots hold zeros); only the stores depend on it
+    const unsigned w = nbr[n];
     const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
     const Pops<P> f(fq, kp);
     real v[27];
@@ -58,6 +61,7 @@ __global__ __launch_bounds__(kBlock) void k_moments_m(KP kp, const unsigned *nbr
     double r;
     real jx, jy, jz;
     moments(v, r, jx, jy, jz);
+    if (solid_at(w)) return;
     rho[n] = r;
     real *j = (real *)jq;
     j[n] = jx;
@@ -102,7 +106,8 @@ __global__ __launch_bounds__(kBlock) void k_wall_rho_m(KP kp, const unsigned *nb
 // mu = mu0(rho) - kappa lap_h rho, lap_h g = 6 sum_i w_i (g(x+c_i) - g(x))
 __global__ __launch_bounds__(kBlock) void k_mu_m(KP kp, const unsigned *nbr, const double *rho, double *mu) {
     const unsigned n = blockIdx.x * kBlock + threadIdx.x;
-    if (n >= kp.N || solid_at(nbr[n])) return;
+    if (n >= kp.N) return;
+    const bool solid = solid_at(nbr[n]);
     int x, y, z;
     decompose(kp, n, x, y, z);
     const Nb nb(kp, x, y, z);
@@ -113,6 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_mu_m(KP kp, const unsigned *nbr, con
         if (i == kRest) continue;
         s += wi(i) * (rho[nb.at(cxi(i), cyi(i), czi(i))] - r0);
     }
+    if (solid) return;
     mu[n] = mu_bulk(kp, r0) - kp.kappa * 6.0 * s;
 }
 
@@ -132,10 +138,7 @@ __global__ __launch_bounds__(kBlock) void k_fphi_m(KP kp, const unsigned *nbr, c
     if (n >= kp.N) return;
     const size_t N = kp.N;
     real *F = (real *)Fq, *phi = (real *)phiq;
-    if (solid_at(nbr[n])) {
-        for (int a = 0; a < 3; ++a) F[a * N + n] = phi[a * N + n] = (real)0;
-        return;
-    }
+    const bool solid = solid_at(nbr[n]);
     int x, y, z;
     decompose(kp, n, x, y, z);
     const Nb nb(kp, x, y, z);
@@ -148,6 +151,10 @@ __global__ __launch_bounds__(kBlock) void k_fphi_m(KP kp, const unsigned *nbr, c
         if (cxi(i)) gx += cxi(i) * v;
         if (cyi(i)) gy += cyi(i) * v;
         if (czi(i)) gz += czi(i) * v;
+    }
+    if (solid) {
+        for (int a = 0; a < 3; ++a) F[a * N + n] = phi[a * N + n] = (real)0;
+        return;
     }
     const double rd = rho[n];
     const double c1 = 1.0 / 3.0 - rd;
@@ -174,10 +181,7 @@ __global__ __launch_bounds__(kBlock) void k_q_m(KP kp, const unsigned *nbr, cons
     if (n >= kp.N) return;
     const size_t N = kp.N;
     real *Q = (real *)Qq;
-    if (solid_at(nbr[n])) {
-        for (int a = 0; a < 3; ++a) Q[a * N + n] = (real)0;
-        return;
-    }
+    const bool solid = solid_at(nbr[n]);
     int x, y, z;
     decompose(kp, n, x, y, z);
     const Nb nb(kp, x, y, z);
@@ -193,9 +197,9 @@ __global__ __launch_bounds__(kBlock) void k_q_m(KP kp, const unsigned *nbr, cons
         if (czi(i)) sz += (real)czi(i) * wt * phi[2 * N + m];
     }
     const real h = (real)(-9.0);
-    Q[n] = h * sx;
-    Q[N + n] = h * sy;
-    Q[2 * N + n] = h * sz;
+    Q[n] = solid ? (real)0 : h * sx;
+    Q[N + n] = solid ? (real)0 : h * sy;
+    Q[2 * N + n] = solid ? (real)0 : h * sz;
 }
 
 template <int P>
@@ -205,7 +209,6 @@ __global__ __launch_bounds__(kBlock) void k_collide_m(KP kp, const unsigned *nbr
     const unsigned n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= kp.N) return;
     const unsigned w = nbr[n];
-    if (solid_at(w)) return;
     int x, y, z;
     decompose(kp, n, x, y, z);
     const Nb nb(kp, x, y, z);
@@ -215,6 +218,7 @@ __global__ __launch_bounds__(kBlock) void k_collide_m(KP kp, const unsigned *nbr
     real f[27];
 #pragma unroll
     for (int i = 0; i < 27; ++i) f[i] = fin.ld(i, row, (unsigned)x);
+    if (solid_at(w)) return;
     const real *F = (const real *)Fq, *Qa = (const real *)Qq;
     collide_node(kp, f, mu[n], F[n], F[kp.N + n], F[2 * (size_t)kp.N + n], Qa[n], Qa[kp.N + n],
                  Qa[2 * (size_t)kp.N + n]);
