@@ -80,6 +80,12 @@ def workload(name, lbfe, torch):
         rho = inputs.sphere((128, 128, 128), (64, 64, 64), 30.0, rl, rv)
         desc = "droplet 128^3 r=30 between walls moving at U=0.1 (x), T=0.8Tc"
         return dict(nx=128, ny=128, nz=128, T=T, walls_z=1, wall_u=(0.1, 0.0, 0.1, 0.0)), rho, None, desc
+    if name == "collision":
+        T = 0.85 * 8 * (9 / 392) / (27 * (2 / 21))
+        rl, rv = lbfe.coexistence(9 / 392, 2 / 21, 1.0, T)
+        rho, u = inputs.head_on_collision(rl, rv)
+        desc = "head-on collision 512^3 periodic, two r=64 droplets 160 apart at +-0.04, T=0.85Tc"
+        return dict(nx=512, ny=512, nz=512, T=T), rho, u, desc
     if name == "pillars":
         T = 0.7 * 8 * (9 / 392) / (27 * (2 / 21))
         rl, rv = lbfe.coexistence(9 / 392, 2 / 21, 1.0, T)

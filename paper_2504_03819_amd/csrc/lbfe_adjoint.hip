@@ -223,7 +223,7 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const void *ft, const void *lam_in,
                                                         void *lam_out) {
     using real = real_t<P>;
-    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    const unsigned idx = tile_id(kp) * kBlock + threadIdx.x;
     if (idx >= kp.nfluid) return;
     const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
     int x, y, z;
@@ -645,7 +645,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_wall_rho_solid(KP kp, const doub
 // lambda_i(t) = direct part + rho_bar_total + c_i . j_bar at fluid nodes.
 template <int P> __global__ __launch_bounds__(kBlock) void k_adj_final(KP kp, Bufs b, void *lam) {
     using real = real_t<P>;
-    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    const unsigned idx = tile_id(kp) * kBlock + threadIdx.x;
     if (idx >= kp.nfluid) return;
     const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
     const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;

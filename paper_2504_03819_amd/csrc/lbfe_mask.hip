@@ -48,7 +48,7 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_moments_m(KP kp, const unsigned *nbr, const void *fq, double *rho,
                                                       void *jq, int *flag) {
     using real = real_t<P>;
-    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    const unsigned n = tile_id(kp) * kBlock + threadIdx.x;
     if (n >= kp.N) return;
     // the population loads do not wait for the neighbour word (a solid
     // node's slots hold zeros); only the stores depend on it
@@ -88,7 +88,7 @@ __device__ inline double fluid_average(const KP &kp, unsigned w, const double *g
 }
 
 __global__ __launch_bounds__(kBlock) void k_wall_rho_m(KP kp, const unsigned *nbr, double *rho) {
-    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    const unsigned n = tile_id(kp) * kBlock + threadIdx.x;
     if (n >= kp.N) return;
     const unsigned w = nbr[n];
     if (!solid_at(w)) return;
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_wall_rho_m(KP kp, const unsigned *nb
 
 // mu = mu0(rho) - kappa lap_h rho, lap_h g = 6 sum_i w_i (g(x+c_i) - g(x))
 __global__ __launch_bounds__(kBlock) void k_mu_m(KP kp, const unsigned *nbr, const double *rho, double *mu) {
-    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    const unsigned n = tile_id(kp) * kBlock + threadIdx.x;
     if (n >= kp.N) return;
     const bool solid = solid_at(nbr[n]);
     int x, y, z;
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_mu_m(KP kp, const unsigned *nbr, con
 }
 
 __global__ __launch_bounds__(kBlock) void k_wall_mu_m(KP kp, const unsigned *nbr, double *mu) {
-    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    const unsigned n = tile_id(kp) * kBlock + threadIdx.x;
     if (n >= kp.N) return;
     const unsigned w = nbr[n];
     if (!solid_at(w)) return;
@@ -134,7 +134,7 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_fphi_m(KP kp, const unsigned *nbr, const double *rho, const void *jq,
                                                    const double *mu, void *Fq, void *phiq) {
     using real = real_t<P>;
-    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    const unsigned n = tile_id(kp) * kBlock + threadIdx.x;
     if (n >= kp.N) return;
     const size_t N = kp.N;
     real *F = (real *)Fq, *phi = (real *)phiq;
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_fphi_m(KP kp, const unsigned *nbr, c
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_q_m(KP kp, const unsigned *nbr, const void *phiq, void *Qq) {
     using real = real_t<P>;
-    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    const unsigned n = tile_id(kp) * kBlock + threadIdx.x;
     if (n >= kp.N) return;
     const size_t N = kp.N;
     real *Q = (real *)Qq;
@@ -206,7 +206,7 @@ template <int P>
 __global__ __launch_bounds__(kBlock) void k_collide_m(KP kp, const unsigned *nbr, const void *fin_q, void *fout_q,
                                                       const double *mu, const void *Fq, const void *Qq) {
     using real = real_t<P>;
-    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    const unsigned n = tile_id(kp) * kBlock + threadIdx.x;
     if (n >= kp.N) return;
     const unsigned w = nbr[n];
     int x, y, z;
