@@ -48,11 +48,15 @@ constexpr unsigned kOOB = 0x80000000u;
 __device__ inline __amdgpu_buffer_rsrc_t plane_rsrc(const void *base, unsigned bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
 }
+// The outputs mu, F, Q are stored non-temporal (cache-policy bit 2): the
+// collide pass reads them once, after the whole chain, and the L2 is left to
+// the stencil halos.
+constexpr int kStoreNT = 2;
 __device__ inline void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, kStoreNT);
 }
 __device__ inline void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, kStoreNT);
 }
 __device__ inline void bload(double &v, __amdgpu_buffer_rsrc_t r, unsigned off) {
     v = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
