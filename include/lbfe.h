@@ -232,6 +232,23 @@ int lbfe_adjoint_get(lbfe_ctx *ctx, double *lambda_dev);
  * Overwrites the auxiliary fields of the context. */
 int lbfe_adjoint_step(lbfe_ctx *ctx, const void *state_t_dev);
 
+/* Forward auxiliary fields kept for the adjoint.  A checkpointed reverse
+ * sweep recomputes f(t) with forward steps; each such step evaluates the
+ * fields of its input state (rho with the wall densities, mu, j, F, Q, steps
+ * S1-S5 of Sec. II B), which lbfe_adjoint_step would otherwise evaluate
+ * again.  lbfe_aux_bytes: size of one record (depends only on the grid and
+ * the storage form).  lbfe_step_aux: one step f(t) -> f(t+1) (unfused) that
+ * leaves the fields of f(t) in aux_dev instead of the workspace; same
+ * result as lbfe_step(ctx, 1), bit for bit, without the divergence check.
+ * lbfe_adjoint_step_aux: lbfe_adjoint_step with the record of f(t) from
+ * lbfe_step_aux; bit for bit the same lambda(t) and gradients, without the
+ * recomputation.  aux_dev: caller-owned device memory of lbfe_aux_bytes,
+ * 256-byte aligned (E_INVAL otherwise); it must be the record of exactly
+ * state_t_dev. */
+int lbfe_aux_bytes(const lbfe_ctx *ctx, size_t *bytes);
+int lbfe_step_aux(lbfe_ctx *ctx, void *aux_dev);
+int lbfe_adjoint_step_aux(lbfe_ctx *ctx, const void *state_t_dev, const void *aux_dev);
+
 /* Pull lambda(0) back through the initialiser of lbfe_init_density given
  * the same rho0_dev and u0_dev (NULL = 0): dL/drho0 into dL_drho0_dev
  * (double[nz][ny][nx], zero at solid nodes); adds the initialiser's kappa and

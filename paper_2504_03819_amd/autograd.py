@@ -8,7 +8,8 @@ backward pass seeds lambda(T) = dL/drho_T, sweeps the adjoint steps in
 reverse and returns dL/drho0, dL/dkappa and dL/d(wet_value).  The forward
 states are recomputed either segment by segment from checkpoints taken every
 `cfg.checkpoint_every` steps (uniform: memory is T/K checkpoints plus K
-states of one segment) or by the binomial schedule of reverse_binomial
+states of one segment, each with the record of its forward auxiliary fields
+when `cfg.keep_aux`) or by the binomial schedule of reverse_binomial
 (memory: `cfg.snapshots` states).  The recomputation is bitwise identical to
 the forward pass, so the gradients do not depend on the schedule.
 
@@ -47,6 +48,10 @@ class StepConfig:
     # (revolve) schedule, for runs whose states do not all fit in memory
     checkpoint: str = "uniform"
     snapshots: int = 8
+    # uniform schedule: keep the forward auxiliary fields of every recomputed
+    # state of a segment (lbfe_step_aux), so the adjoint steps skip their
+    # recomputation; costs one aux record per state held
+    keep_aux: bool = True
 
     def make(self, kappa, wet_value):
         return lbfe.Simulation(device=self.device, nx=self.nx, ny=self.ny, nz=self.nz, T=self.T, nu=self.nu,
@@ -136,12 +141,20 @@ class LBFEFunction(torch.autograd.Function):
                 s1 = min(s0 + K, cfg.steps)
                 sim.set_state(ctx.checkpoints[s0], s0)
                 states = [sim.get_state().clone()]
+                recs = []
                 for _ in range(s0 + 1, s1):
-                    sim.step(1)
+                    if cfg.keep_aux:
+                        recs.append(sim.aux_record())
+                        sim.step_aux(recs[-1])
+                    else:
+                        sim.step(1)
                     states.append(sim.get_state().clone())
                 for t in range(s1 - 1, s0 - 1, -1):
-                    sim.adjoint_step(states[t - s0])
-                del states
+                    if t - s0 < len(recs):
+                        sim.adjoint_step_aux(states[t - s0], recs[t - s0])
+                    else:  # the segment's last state was never stepped from
+                        sim.adjoint_step(states[t - s0])
+                del states, recs
         g_rho0 = sim.adjoint_init_density(rho0.detach(), cfg.u0)
         g = sim.adjoint_grads()
         dev = grad_rho.device

@@ -873,11 +873,14 @@ hipError_t launch_adj_get(hipStream_t s, int prec, const KP &kp, const Bufs &b, 
     });
 }
 
-hipError_t launch_adj_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const void *ft) {
-    Bufs fb = b;
-    fb.f[0] = const_cast<void *>(ft);
-    hipError_t e = launch_aux(s, prec, kp, fb, 0);
-    if (e != hipSuccess) return e;
+hipError_t launch_adj_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const void *ft,
+                           bool recompute) {
+    if (recompute) {
+        Bufs fb = b;
+        fb.f[0] = const_cast<void *>(ft);
+        hipError_t e = launch_aux(s, prec, kp, fb, 0);
+        if (e != hipSuccess) return e;
+    }
     const unsigned gf = nblocks(kp.nfluid);
     double *A = (double *)b.abuf;
     return dispatch(prec, [&](auto pc) {

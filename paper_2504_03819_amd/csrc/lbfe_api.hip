@@ -191,6 +191,39 @@ int read_flag(lbfe_ctx *c, int &flag) {
     return LBFE_OK;
 }
 
+// One record of forward auxiliary fields: rho, mu (double, N each), then
+// j, F, Q (3 N each, compute precision), sub-buffers 256-byte aligned.
+struct AuxLayout {
+    size_t rho, mu, j, F, Q, total;
+};
+
+AuxLayout aux_layout(const lbfe_params &p) {
+    const size_t N = (size_t)p.nx * p.ny * p.nz, rb = real_bytes(p.precision);
+    AuxLayout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o += al(bytes); return r; };
+    L.rho = take(8 * N);
+    L.mu = take(8 * N);
+    L.j = take(3 * rb * N);
+    L.F = take(3 * rb * N);
+    L.Q = take(3 * rb * N);
+    L.total = o;
+    return L;
+}
+
+// the context's buffers with the aux fields redirected into a record
+Bufs with_aux(const lbfe_ctx *c, const void *aux) {
+    const AuxLayout L = aux_layout(c->p);
+    char *a = (char *)const_cast<void *>(aux);
+    Bufs b = c->b;
+    b.rho = (double *)(a + L.rho);
+    b.mu = (double *)(a + L.mu);
+    b.j = a + L.j;
+    b.F = a + L.F;
+    b.Q = a + L.Q;
+    return b;
+}
+
 }  // namespace
 
 extern "C" {
@@ -587,8 +620,39 @@ int lbfe_adjoint_step(lbfe_ctx *c, const void *ft) {
     if (!c->adj_seeded) return fail(c, LBFE_E_STATE, "adjoint not seeded");
     if (!ft) return fail(c, LBFE_E_INVAL, "null state");
     c->aux_ok = false;  // the recomputation below overwrites rho, j, mu0
-    hipError_t e = launch_adj_step(c->stream, c->p.precision, c->kp, c->b, c->lcur, ft);
+    hipError_t e = launch_adj_step(c->stream, c->p.precision, c->kp, c->b, c->lcur, ft, true);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
+    c->lcur ^= 1;
+    return LBFE_OK;
+}
+
+int lbfe_aux_bytes(const lbfe_ctx *c, size_t *bytes) {
+    if (!c || !bytes) return LBFE_E_INVAL;
+    *bytes = aux_layout(c->p).total;
+    return LBFE_OK;
+}
+
+int lbfe_step_aux(lbfe_ctx *c, void *aux) {
+    int r = need_init(c);
+    if (r) return r;
+    if (!aux || ((uintptr_t)aux & 255u)) return fail(c, LBFE_E_INVAL, "aux record null or not 256-byte aligned");
+    hipError_t e = launch_step(c->stream, c->p.precision, c->kp, with_aux(c, aux), c->cur, false, true, nullptr);
+    if (e != hipSuccess) return hip_fail(c, e, "step_aux");
+    c->cur ^= 1;
+    c->step++;
+    c->aux_ok = false;  // the workspace fields do not describe the new state
+    return LBFE_OK;
+}
+
+int lbfe_adjoint_step_aux(lbfe_ctx *c, const void *ft, const void *aux) {
+    int r = need_bound(c);
+    if (r) return r;
+    if (!c->p.adjoint) return fail(c, LBFE_E_STATE, "created without params.adjoint = 1");
+    if (!c->adj_seeded) return fail(c, LBFE_E_STATE, "adjoint not seeded");
+    if (!ft) return fail(c, LBFE_E_INVAL, "null state");
+    if (!aux || ((uintptr_t)aux & 255u)) return fail(c, LBFE_E_INVAL, "aux record null or not 256-byte aligned");
+    hipError_t e = launch_adj_step(c->stream, c->p.precision, c->kp, with_aux(c, aux), c->lcur, ft, false);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint_step_aux");
     c->lcur ^= 1;
     return LBFE_OK;
 }

@@ -89,7 +89,9 @@ size_t adjoint_grad_slots();
 hipError_t launch_adj_seed(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const double *dLdrho);
 hipError_t launch_adj_seed_pop(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const double *lam);
 hipError_t launch_adj_get(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, double *out);
-hipError_t launch_adj_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const void *ft);
+// recompute: evaluate the forward fields of ft first (else b holds them)
+hipError_t launch_adj_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const void *ft,
+                           bool recompute);
 hipError_t launch_adj_init(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const double *rho0,
                            const double *u0, double *out);
 

@@ -79,6 +79,9 @@ def lib():
         "lbfe_adjoint_get": (c_int, [V, V]),
         "lbfe_adjoint_init_density": (c_int, [V, V, V, V]),
         "lbfe_adjoint_grads": (c_int, [V, POINTER(c_double)]),
+        "lbfe_aux_bytes": (c_int, [V, POINTER(c_size_t)]),
+        "lbfe_step_aux": (c_int, [V, V]),
+        "lbfe_adjoint_step_aux": (c_int, [V, V, V]),
         "lbfe_last_error": (ctypes.c_char_p, [V]),
         "lbfe_destroy": (c_int, [V]),
     }
@@ -275,6 +278,24 @@ class Simulation:
 
     def adjoint_step(self, state_t):
         self._check(lib().lbfe_adjoint_step(self._ctx, _ptr(state_t)))
+
+    # ------------------------------------- forward fields kept for the adjoint --
+    def aux_record(self):
+        """A device buffer (uint8, 256-byte aligned view) for one record of
+        the forward auxiliary fields (lbfe_aux_bytes)."""
+        n = c_size_t()
+        self._check(lib().lbfe_aux_bytes(self._ctx, byref(n)))
+        raw = self._torch.empty(n.value + 256, dtype=self._torch.uint8, device=self.device)
+        off = (-raw.data_ptr()) % 256
+        return raw[off:off + n.value]
+
+    def step_aux(self, record):
+        """One step; the fields of the state before it go into `record`."""
+        self._check(lib().lbfe_step_aux(self._ctx, _ptr(record)))
+
+    def adjoint_step_aux(self, state_t, record):
+        """adjoint_step with the record that step_aux left for state_t."""
+        self._check(lib().lbfe_adjoint_step_aux(self._ctx, _ptr(state_t), _ptr(record)))
 
     def adjoint_init_density(self, rho0=None, u0=None):
         """dL/drho0 for the initial state made by init_density (the rho0 and

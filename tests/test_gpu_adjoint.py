@@ -158,14 +158,16 @@ def test_end_to_end_gradients_vs_oracle_and_fd(walls, wet_mode, wet_value):
 
 
 def test_checkpoint_interval_does_not_change_gradients():
-    """Uniform checkpoints every 1, 4, 9 steps and the binomial schedule with
-    two snapshots give bitwise identical gradients."""
+    """Uniform checkpoints every 1, 4, 9 steps (with and without the kept
+    forward fields) and the binomial schedule with two snapshots give
+    bitwise identical gradients."""
     shape = (10, 8, 8)
     rho0, tgt, cfg = _loss_setup(shape, True, 1, 1.3, 9)
     grads = []
-    for K, mode in ((1, "uniform"), (4, "uniform"), (9, "uniform"), (0, "binomial")):
+    for K, mode, keep in ((1, "uniform", True), (4, "uniform", True), (4, "uniform", False), (9, "uniform", True),
+                          (9, "uniform", False), (0, "binomial", False)):
         cfg.checkpoint_every = max(K, 1)
-        cfg.checkpoint, cfg.snapshots = mode, 2
+        cfg.checkpoint, cfg.snapshots, cfg.keep_aux = mode, 2, keep
         r0 = torch.tensor(rho0, device="cuda", requires_grad=True)
         kap = torch.tensor(0.02, dtype=DT, requires_grad=True)
         wet = torch.tensor(1.3, dtype=DT, requires_grad=True)
@@ -195,3 +197,36 @@ def test_fp32_adjoint_close_to_fp64():
     ew = abs(out["fp32"][2] - out["fp64"][2]) / abs(out["fp64"][2])
     say(f"fp32 vs fp64 adjoint: drho0 {e:.2e} dkappa {ek:.2e} dwet {ew:.2e}")
     assert e < 1e-4 and ek < 1e-4 and ew < 1e-4
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+def test_adjoint_step_with_kept_aux_is_bitwise_the_same(form):
+    """lbfe_step_aux + lbfe_adjoint_step_aux against lbfe_step +
+    lbfe_adjoint_step (recomputed fields) over 6 steps of a walled droplet:
+    the same forward state, lambda and parameter gradients bit for bit."""
+    shape = (10, 9, 11)
+    T = eos.temperature(0.7)
+    rho0 = droplet_rho(shape, T, walls=True, radius=3.5, noise=1e-2, seed=3)
+    kw = dict(nx=11, ny=9, nz=10, T=T, walls_z=1, wet_mode=1, wet_value=1.3, precision=form, adjoint=1)
+    a, b = make_sim(**kw), make_sim(**kw)
+    states, recs = [], []
+    for s in (a, b):
+        s.init_density(torch.tensor(rho0))
+    for _ in range(6):
+        states.append(a.get_state().clone())
+        a.step(1)
+        recs.append(b.aux_record())
+        b.step_aux(recs[-1])
+    assert torch.equal(a.get_state(), b.get_state())
+    g = torch.tensor(inputs.uniform_noise(shape, 1.0, 7), device="cuda")
+    a.adjoint_seed(g)
+    b.adjoint_seed(g)
+    for t in range(5, -1, -1):
+        a.adjoint_step(states[t])
+        b.adjoint_step_aux(states[t], recs[t])
+    assert torch.equal(a.adjoint_state().cpu(), b.adjoint_state().cpu())
+    assert a.adjoint_grads() == b.adjoint_grads()
+    bad = b.aux_record()
+    with pytest.raises(lbfe.LBFEError) as e:
+        b.adjoint_step_aux(states[0], bad[8:])
+    assert e.value.code == lbfe.E_INVAL
