@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
 }
 
 // ---------------------------------------------------------------------------
-// z-marching tiles for the transposed stencils.  A workgroup owns a 32 x 8
+// z-marching tiles for the transposed stencils.  A workgroup owns a 32 x 16
 // column tile of one z-chunk.  The stencil inputs of four consecutive planes
 // (tile + one-node halo) sit in an LDS ring; plane k+2 is loaded into
 // registers while plane k is evaluated, so one barrier per plane suffices
@@ -332,7 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
 // wrap periodically, as in the forward kernels; in a walled box the
 // wrapped planes are solid and the fields read there are zero or unused.
 // ---------------------------------------------------------------------------
-constexpr int ZTX = 32, ZTY = 8, ZWX = ZTX + 2, ZNR = ZWX * (ZTY + 2), ZCB = ZTX * ZTY;
+constexpr int ZTX = 32, ZTY = 16, ZWX = ZTX + 2, ZNR = ZWX * (ZTY + 2), ZCB = ZTX * ZTY;
 constexpr int ZM = (ZNR + ZCB - 1) / ZCB;  // halo-region points per thread
 
 __device__ inline int zwrap(int v, int n) {

@@ -6,7 +6,7 @@
 //           u = (j + F/2)/rho, phi = (p_m - rho/3) u
 //   phi  -> Q_aa = -3 d_a phi_a                              (Eq. (27))
 //
-// Each workgroup owns a TX x TY column tile and marches in z over a chunk of
+// Each workgroup owns a 64 x 16 column tile and marches in z over a chunk of
 // planes.  The isotropic D3Q27 stencils factor into D1Q3 pieces (weights
 // 1/6, 2/3, 1/6 along each axis), so every stencil is evaluated as an
 // in-plane part, read from one LDS plane, and a z part, combined in a
@@ -27,7 +27,7 @@
 namespace lbfe {
 namespace {
 
-constexpr int TX = 32, TY = 16;
+constexpr int TX = 64, TY = 16;  // 1024 threads, one workgroup per CU (LDS)
 constexpr int CB = TX * TY;                            // threads: one per tile column
 constexpr int WR = TX + 8, HR = TY + 8, NR = WR * HR;  // rho region (halo 4)
 constexpr int WM = TX + 6, HM = TY + 6, NM = WM * HM;  // mu region (halo 3)
