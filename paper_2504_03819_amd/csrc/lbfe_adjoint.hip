@@ -16,7 +16,9 @@
 //   k_adj_wall_mu   (walls) wall average of Eq. (36) transposed
 //   k_adj_rho       mu0'(rho) and the (symmetric) Laplacian transposed
 //   k_adj_wall_rho* (walls) limiter/window of Eqs. (37)-(38) transposed
-//   k_adj_final     lambda_i(t) += rho_bar + c_i . j_bar
+//   k_adj_final     lambda_i(t) += rho_bar + c_i . j_bar, applied when lambda
+//                   is read out; between adjoint steps this term is added by
+//                   the next step's gather instead
 //   k_adj_reduce*   deterministic parameter-gradient accumulation
 #include <type_traits>
 
@@ -43,7 +45,8 @@ enum : int {
     A_RAVEB = 21,// rho_ave bar at solid nodes
     A_RHOBT = 22,// rho bar total (all nodes)
     A_MUBT = 23, // mu bar total (all nodes)
-    A_COUNT = 24
+    A_PACK = 24, // 4 planes: (rho_bar_total, j_bar) per node as 4 compute-precision values
+    A_COUNT = 28
 };
 
 // Adjoint (lambda) storage: same row-blocked layout as the populations, in
@@ -218,8 +221,49 @@ __device__ inline void collide_T(real (&l)[27], const real (&k)[27], const Rates
     l[K(2, 2, 2)] *= (one - w[10]);
 }
 
+// The last term of lambda(t): lambda_i(x) = direct part + rho_bar_total(x)
+// + c_i . j_bar(x) at fluid nodes.  It is either applied in place
+// (k_adj_final) or, while the next adjoint step follows, added to each value
+// as that step gathers it (k_adj_collide with PEND): the same expression in
+// the same order, so both give lambda bit for bit.
+template <class real> __device__ inline real final_term(real rb, real jx, real jy, real jz, int i) {
+    real add = rb;
+    if (cxi(i)) add += (real)cxi(i) * jx;
+    if (cyi(i)) add += (real)cyi(i) * jy;
+    if (czi(i)) add += (real)czi(i) * jz;
+    return add;
+}
+template <class real> __device__ inline real final_term(const double *A, size_t N, int i, size_t m) {
+    return final_term<real>((real)A[A_RHOBT * N + m], (real)A[A_JB * N + m], (real)A[(A_JB + 1) * N + m],
+                            (real)A[(A_JB + 2) * N + m], i);
+}
+// the same four values packed per node (k_adj_pack), one vector load
+template <class real> using Pack4 = std::conditional_t<std::is_same_v<real, double>, double4, float4>;
+template <class real> __device__ inline real final_term(const Pack4<real> *pk, int i, size_t m) {
+    const Pack4<real> t = pk[m];
+    return final_term<real>(t.x, t.y, t.z, t.w, i);
+}
+
+template <int P> __global__ __launch_bounds__(kBlock) void k_adj_pack(KP kp, Bufs b) {
+    using real = real_t<P>;
+    const unsigned idx = tile_id(kp) * kBlock + threadIdx.x;
+    if (idx >= kp.nfluid) return;
+    const size_t n = (size_t)kp.z0 * kp.plane + idx, N = kp.N;
+    const double *A = (const double *)b.abuf;
+    Pack4<real> *pk = (Pack4<real> *)(A + A_PACK * N);
+    Pack4<real> t;
+    t.x = (real)A[A_RHOBT * N + n];
+    t.y = (real)A[A_JB * N + n];
+    t.z = (real)A[(A_JB + 1) * N + n];
+    t.w = (real)A[(A_JB + 2) * N + n];
+    pk[n] = t;
+}
+
 // ---------------------------------------------------------------------------
-template <int P>
+// PEND: lam_in holds only the direct part of lambda(t+1); its last term is
+// added during the gather from the (rho_bar_total, j_bar) pack that the
+// previous adjoint step left (this kernel does not write it).
+template <int P, bool PEND>
 __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const void *ft, const void *lam_in,
                                                         void *lam_out) {
     using real = real_t<P>;
@@ -272,13 +316,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     const bool wall_lo = kp.walls && z == 1;
     const bool wall_hi = kp.walls && z == kp.nz - 2;
     real l[27];
+    const Pack4<real> *pk = (const Pack4<real> *)((const double *)b.abuf + A_PACK * (size_t)kp.N);
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int cz = czi(i);
-        if ((cz < 0 && wall_lo) || (cz > 0 && wall_hi))
+        if ((cz < 0 && wall_lo) || (cz > 0 && wall_hi)) {
             l[i] = lin.ld(26 - i, row, (unsigned)x);
-        else
+            if constexpr (PEND) l[i] += final_term<real>(pk, 26 - i, n);
+        } else {
             l[i] = lin.ld(i, nb.row(cyi(i), cz), nb.xo(cxi(i)));
+            if constexpr (PEND) l[i] += final_term<real>(pk, i, nb.at(cxi(i), cyi(i), cz));
+        }
     }
     cm_inverse_T(l, ux, uy, uz);  // l = lambda_hat (adjoint of k*)
     real ubx, uby, ubz;
@@ -651,17 +699,9 @@ template <int P> __global__ __launch_bounds__(kBlock) void k_adj_final(KP kp, Bu
     const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
     const size_t N = kp.N;
     const double *A = (const double *)b.abuf;
-    const real rb = (real)A[A_RHOBT * N + n];
-    const real jx = (real)A[A_JB * N + n], jy = (real)A[(A_JB + 1) * N + n], jz = (real)A[(A_JB + 2) * N + n];
     const Lam<real> L(lam, kp);
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        real add = rb;
-        if (cxi(i)) add += (real)cxi(i) * jx;
-        if (cyi(i)) add += (real)cyi(i) * jy;
-        if (czi(i)) add += (real)czi(i) * jz;
-        L.st(i, row, x, L.ld(i, row, x) + add);
-    }
+    for (int i = 0; i < 27; ++i) L.st(i, row, x, L.ld(i, row, x) + final_term<real>(A, N, i, n));
 }
 
 // Deterministic accumulation: per-block sums of three per-node arrays, then
@@ -874,7 +914,7 @@ hipError_t launch_adj_get(hipStream_t s, int prec, const KP &kp, const Bufs &b, 
 }
 
 hipError_t launch_adj_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const void *ft,
-                           bool recompute) {
+                           bool recompute, bool pending) {
     if (recompute) {
         Bufs fb = b;
         fb.f[0] = const_cast<void *>(ft);
@@ -885,11 +925,22 @@ hipError_t launch_adj_step(hipStream_t s, int prec, const KP &kp, const Bufs &b,
     double *A = (double *)b.abuf;
     return dispatch(prec, [&](auto pc) {
         constexpr int P = decltype(pc)::value;
-        k_adj_collide<P><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
+        if (pending)
+            k_adj_collide<P, true><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
+        else
+            k_adj_collide<P, false><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
         k_adj_phi<P><<<zgrid(kp, kp.z0, kp.z1), ZCB, 0, s>>>(kp, b, kZChunk);
         hipError_t r = chain_tail(s, kp, b, true, A + A_NUC * (size_t)kp.N);
         if (r != hipSuccess) return r;
-        k_adj_final<P><<<gf, kBlock, 0, s>>>(kp, b, b.lam[1 - lcur]);
+        k_adj_pack<P><<<gf, kBlock, 0, s>>>(kp, b);
+        return hipGetLastError();  // lambda(t) = direct part; its last term is pending
+    });
+}
+
+hipError_t launch_adj_finalize(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur) {
+    return dispatch(prec, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        k_adj_final<P><<<nblocks(kp.nfluid), kBlock, 0, s>>>(kp, b, b.lam[lcur]);
         return hipGetLastError();
     });
 }

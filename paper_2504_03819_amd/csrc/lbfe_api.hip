@@ -28,6 +28,7 @@ struct lbfe_ctx {
     bool fused = false;   // fused collide-stream-moments step (LBFE_FUSED=1)
     bool aux_ok = false;  // rho, j, mu0 hold the moments of f[cur]
     bool mask_set = false;  // a solid mask has been given (solid_mask = 1)
+    bool lam_pending = false;  // lam[lcur] lacks its last term (see the adjoint kernels)
     std::string err;
 };
 
@@ -188,6 +189,16 @@ int read_flag(lbfe_ctx *c, int &flag) {
     hipError_t e = hipMemcpyAsync(&flag, c->b.flag, sizeof(int), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "flag readback");
+    return LBFE_OK;
+}
+
+// Completes lambda(t) in place when its last term is still pending (before
+// lambda is read out or the auxiliary planes are reused).
+int finalize_lambda(lbfe_ctx *c) {
+    if (!c->lam_pending) return LBFE_OK;
+    hipError_t e = launch_adj_finalize(c->stream, c->p.precision, c->kp, c->b, c->lcur);
+    if (e != hipSuccess) return hip_fail(c, e, "adjoint finalize");
+    c->lam_pending = false;
     return LBFE_OK;
 }
 
@@ -584,6 +595,7 @@ int lbfe_adjoint_seed(lbfe_ctx *c, const double *dLdrho) {
     if (!c->p.adjoint) return fail(c, LBFE_E_STATE, "created without params.adjoint = 1");
     if (!dLdrho) return fail(c, LBFE_E_INVAL, "null dL/drho");
     c->lcur = 0;
+    c->lam_pending = false;
     hipError_t e = launch_adj_seed(c->stream, c->p.precision, c->kp, c->b, c->lcur, dLdrho);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_seed");
     c->adj_seeded = true;
@@ -596,6 +608,7 @@ int lbfe_adjoint_seed_populations(lbfe_ctx *c, const double *g) {
     if (!c->p.adjoint) return fail(c, LBFE_E_STATE, "created without params.adjoint = 1");
     if (!g) return fail(c, LBFE_E_INVAL, "null dL/df");
     c->lcur = 0;
+    c->lam_pending = false;
     hipError_t e = launch_adj_seed_pop(c->stream, c->p.precision, c->kp, c->b, c->lcur, g);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_seed_populations");
     c->adj_seeded = true;
@@ -608,6 +621,7 @@ int lbfe_adjoint_get(lbfe_ctx *c, double *out) {
     if (!c->p.adjoint) return fail(c, LBFE_E_STATE, "created without params.adjoint = 1");
     if (!c->adj_seeded) return fail(c, LBFE_E_STATE, "adjoint not seeded");
     if (!out) return fail(c, LBFE_E_INVAL, "null output");
+    if ((r = finalize_lambda(c))) return r;
     hipError_t e = launch_adj_get(c->stream, c->p.precision, c->kp, c->b, c->lcur, out);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_get");
     return LBFE_OK;
@@ -620,9 +634,10 @@ int lbfe_adjoint_step(lbfe_ctx *c, const void *ft) {
     if (!c->adj_seeded) return fail(c, LBFE_E_STATE, "adjoint not seeded");
     if (!ft) return fail(c, LBFE_E_INVAL, "null state");
     c->aux_ok = false;  // the recomputation below overwrites rho, j, mu0
-    hipError_t e = launch_adj_step(c->stream, c->p.precision, c->kp, c->b, c->lcur, ft, true);
+    hipError_t e = launch_adj_step(c->stream, c->p.precision, c->kp, c->b, c->lcur, ft, true, c->lam_pending);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");
     c->lcur ^= 1;
+    c->lam_pending = true;
     return LBFE_OK;
 }
 
@@ -651,9 +666,11 @@ int lbfe_adjoint_step_aux(lbfe_ctx *c, const void *ft, const void *aux) {
     if (!c->adj_seeded) return fail(c, LBFE_E_STATE, "adjoint not seeded");
     if (!ft) return fail(c, LBFE_E_INVAL, "null state");
     if (!aux || ((uintptr_t)aux & 255u)) return fail(c, LBFE_E_INVAL, "aux record null or not 256-byte aligned");
-    hipError_t e = launch_adj_step(c->stream, c->p.precision, c->kp, with_aux(c, aux), c->lcur, ft, false);
+    hipError_t e =
+        launch_adj_step(c->stream, c->p.precision, c->kp, with_aux(c, aux), c->lcur, ft, false, c->lam_pending);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_step_aux");
     c->lcur ^= 1;
+    c->lam_pending = true;
     return LBFE_OK;
 }
 
@@ -663,6 +680,7 @@ int lbfe_adjoint_init_density(lbfe_ctx *c, const double *rho0, const double *u0,
     if (!c->p.adjoint) return fail(c, LBFE_E_STATE, "created without params.adjoint = 1");
     if (!c->adj_seeded) return fail(c, LBFE_E_STATE, "adjoint not seeded");
     if (!rho0 || !out) return fail(c, LBFE_E_INVAL, "null rho0 or output");
+    if ((r = finalize_lambda(c))) return r;
     c->aux_ok = false;
     hipError_t e = launch_adj_init(c->stream, c->p.precision, c->kp, c->b, c->lcur, rho0, u0, out);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_init_density");

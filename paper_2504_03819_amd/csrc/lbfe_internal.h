@@ -89,9 +89,13 @@ size_t adjoint_grad_slots();
 hipError_t launch_adj_seed(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const double *dLdrho);
 hipError_t launch_adj_seed_pop(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const double *lam);
 hipError_t launch_adj_get(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, double *out);
-// recompute: evaluate the forward fields of ft first (else b holds them)
+// recompute: evaluate the forward fields of ft first (else b holds them);
+// pending: lam[lcur] holds only the direct part of lambda(t+1).  Leaves
+// lam[1 - lcur] as the direct part of lambda(t), its last term pending.
 hipError_t launch_adj_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const void *ft,
-                           bool recompute);
+                           bool recompute, bool pending);
+// applies the pending last term to lam[lcur] in place
+hipError_t launch_adj_finalize(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur);
 hipError_t launch_adj_init(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, const double *rho0,
                            const double *u0, double *out);
 
