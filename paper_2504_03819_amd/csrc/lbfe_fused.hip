@@ -28,6 +28,7 @@
 #include <type_traits>
 
 #include "lbfe_device.h"
+#include "lbfe_dpp.h"
 
 namespace lbfe {
 namespace {
@@ -41,25 +42,6 @@ template <int RY> struct Geo {
     static constexpr int NT = 64 * (RY / 2 + 2);
     static constexpr int NROW = RY + 2;    // rows -1 .. RY
 };
-
-__device__ inline float shr1(float v) {  // lane l gets lane l-1
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xF, 0xF, false));
-}
-__device__ inline float shl1(float v) {  // lane l gets lane l+1
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xF, 0xF, false));
-}
-__device__ inline double shr1(double v) {
-    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, 0x138, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x138, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
-__device__ inline double shl1(double v) {
-    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, 0x130, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), 0x130, 0xF, 0xF, false);
-    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
-}
 
 __device__ inline int wrapi(int v, int n) {
     v %= n;
