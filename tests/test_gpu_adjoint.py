@@ -230,3 +230,42 @@ def test_adjoint_step_with_kept_aux_is_bitwise_the_same(form):
     with pytest.raises(lbfe.LBFEError) as e:
         b.adjoint_step_aux(states[0], bad[8:])
     assert e.value.code == lbfe.E_INVAL
+
+
+def test_reading_lambda_mid_sweep_changes_nothing():
+    """lambda(t) is left without its last term between adjoint steps (the
+    next step's gather adds it); reading it out completes it in place.  A
+    sweep interrupted by adjoint_state() after every step, and one restarted
+    through the population seed, end bit for bit where an uninterrupted
+    sweep does."""
+    shape = (9, 8, 10)
+    T = eos.temperature(0.7)
+    rho0 = droplet_rho(shape, T, walls=True, radius=3.0, noise=1e-2, seed=5)
+    kw = dict(nx=10, ny=8, nz=9, T=T, walls_z=1, wet_mode=2, wet_value=0.6, adjoint=1)
+    sims = [make_sim(**kw) for _ in range(3)]
+    states = []
+    for s in sims:
+        s.init_density(torch.tensor(rho0))
+    for _ in range(5):
+        states.append(sims[0].get_state().clone())
+        for s in sims:
+            s.step(1)
+    g = torch.tensor(inputs.uniform_noise(shape, 1.0, 11), device="cuda")
+    for s in sims:
+        s.adjoint_seed(g)
+    mids = []
+    lam3 = None
+    for t in range(4, -1, -1):
+        sims[0].adjoint_step(states[t])
+        sims[1].adjoint_step(states[t])
+        mids.append(sims[1].adjoint_state().clone())  # completes lambda(t) in place
+        if t == 3:
+            lam3 = mids[-1]
+    # the third context starts at lambda(3) through the general seed
+    sims[2].adjoint_seed_populations(lam3)
+    for t in range(2, -1, -1):
+        sims[2].adjoint_step(states[t])
+    a, b, c = (s.adjoint_state().cpu() for s in sims)
+    assert torch.equal(a, b) and torch.equal(a, c)
+    assert torch.equal(mids[-1].cpu(), a)
+    assert sims[0].adjoint_grads() == sims[1].adjoint_grads()
