@@ -43,6 +43,22 @@ template <int RY> struct Geo {
     static constexpr int NROW = RY + 2;    // rows -1 .. RY
 };
 
+// Ordinary (cached) population loads: unlike the single-pass kernels, this
+// one reads the one-node ring of its tile that the neighbouring tiles read
+// too, and those re-reads should hit the cache.
+__device__ inline double ld_cached(const Pops<LBFE_FP64> &f, int i, unsigned row, unsigned x) {
+    return f.p[f.off(i, row, x)];
+}
+__device__ inline float ld_cached(const Pops<LBFE_FP32> &f, int i, unsigned row, unsigned x) {
+    return f.p[f.off(i, row, x)];
+}
+__device__ inline float ld_cached(const Pops<LBFE_FP16_DEV> &f, int i, unsigned row, unsigned x) {
+    return dec16(i, f.p[f.off(i, row, x)]);
+}
+__device__ inline float ld_cached(const Pops<LBFE_FP16_DEV_F0FP32> &f, int i, unsigned row, unsigned x) {
+    return i == kRest ? f.p0[(size_t)row * f.nx + x] : dec16(i, f.p[f.off(i, row, x)]);
+}
+
 __device__ inline int wrapi(int v, int n) {
     v %= n;
     return v < 0 ? v + n : v;
@@ -126,7 +142,7 @@ __global__ __launch_bounds__(Geo<RY>::NT) void k_fused(KP kp, const void *fin_q,
         const int zz = zw(s);
         const unsigned row = (unsigned)zz * (unsigned)kp.ny + (unsigned)y;
 #pragma unroll
-        for (int i = 0; i < 27; ++i) f[i] = fin.ld(i, row, (unsigned)x);
+        for (int i = 0; i < 27; ++i) f[i] = ld_cached(fin, i, row, (unsigned)x);
         const size_t n = (size_t)row * kp.nx + x;
         m = mu[n];
         Fx = F[n];
