@@ -159,9 +159,11 @@ int lbfe_init_density(lbfe_ctx *ctx, const double *rho0_dev, const double *u0_de
  * bounce-back.  Checks the divergence flag every check_every steps and at
  * the end (a synchronisation): E_DIVERGED, with the step in lbfe_last_error.
  * Each step is a moments pass, the stencil chain and a collide-stream
- * pass; the environment variable LBFE_FUSED=1 at lbfe_create selects a
- * path whose collide-stream kernel also forms the next step's density and
- * momentum (no moments pass), which gives bitwise identical states. */
+ * pass, or, for FP64 contexts of at least 2^24 nodes without moving walls
+ * or a mask, the stencil chain and a collide-stream kernel that also forms
+ * the next step's density and momentum (no moments pass); both give
+ * bitwise identical states.  The environment variable LBFE_FUSED=0/1 at
+ * lbfe_create forces the first or the second path. */
 int lbfe_step(lbfe_ctx *ctx, int64_t nsteps);
 
 /* Timing variant of lbfe_step for benchmarks: the same launches, with HIP

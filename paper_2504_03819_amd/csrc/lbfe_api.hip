@@ -341,15 +341,17 @@ int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out) {
     // LBFE_XCD_REMAP=0/1 forces it.
     const char *remap = std::getenv("LBFE_XCD_REMAP");
     k.xcd_remap = (remap && remap[0]) ? (remap[0] == '1') : (k.N >= (1u << 26));
-    // Step path: separate moments and collide-stream passes by default;
-    // LBFE_FUSED=1 selects the fused collide-stream-moments kernel.  Both
-    // give bitwise identical states.  The fused kernel removes the moments
-    // pass's population read but re-reads a one-node ring of populations per
-    // tile and needs twice the vector instructions per node at two waves per
-    // SIMD; measured on gfx950 it is on par in FP64 and slower in the FP32
-    // and FP16 forms.
+    // Step path: separate moments and collide-stream passes, or the fused
+    // collide-stream-moments kernel, which saves the moments pass's
+    // population read but re-reads a one-node ring of populations per tile
+    // and runs twice the vector instructions per node at two waves per SIMD.
+    // Measured on gfx950 the fused step is faster only in FP64 on large grids
+    // (+3 % at 256^3, +7 % at 512^3) and slower at 128^3 and in the FP32 and
+    // FP16 forms, so it is chosen for FP64 from 2^24 nodes; LBFE_FUSED=0/1
+    // forces either path.  Both give bitwise identical states.
     const char *fu = std::getenv("LBFE_FUSED");
-    c->fused = fu && fu[0] == '1' && !k.moving && !k.masked;  // resting walls, no mask
+    const bool want = (fu && fu[0]) ? fu[0] == '1' : (q.precision == LBFE_FP64 && k.N >= (1u << 24));
+    c->fused = want && !k.moving && !k.masked;  // the fused kernel has resting walls and no mask
     *out = c;
     return LBFE_OK;
 }

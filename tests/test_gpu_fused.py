@@ -26,8 +26,7 @@ CASES = [
 
 
 def _sim(unfused, **kw):
-    if not unfused:
-        os.environ["LBFE_FUSED"] = "1"
+    os.environ["LBFE_FUSED"] = "0" if unfused else "1"
     try:
         return make_sim(**kw)
     finally:
