@@ -223,3 +223,42 @@ def test_contact_angle(mode, value, lo, hi):
     say(f"contact angle mode={mode} value={value}: theta={th:.2f} deg (cap radius {Rf:.1f}), mu spread {mu.max() - mu.min():.1e}")
     assert lo <= th <= hi
     assert mu.max() - mu.min() < 1e-3
+
+
+@pytest.mark.parametrize("label,mode,value", [("hydrophobic", lbfe.WET_DELTA, 0.9), ("hydrophilic", lbfe.WET_PHI, 1.6)])
+def test_droplet_on_pillars_cassie_or_wenzel(label, mode, value):
+    """The wetting boundary on a patterned substrate (solid mask: plate of 2
+    layers, 4 x 4 x 8 pillars at pitch 12, 96 x 96 x 48 box, 0.8 T_c): a
+    droplet (r = 18) placed on the pillar tops stays suspended over vapour
+    on a hydrophobic substrate (drho = 0.9, Cassie state) and fills the gaps
+    between the pillars on a hydrophilic one (phi = 1.6, Wenzel state);
+    the fluid mass is conserved either way."""
+    shape = (48, 96, 96)
+    plate, height = 2, 8
+    top = plate + height
+    mask = inputs.mask_pillars(shape, plate=plate, pitch=12, width=4, height=height)
+    T = eos.temperature(0.8)
+    sim = make_sim(nx=96, ny=96, nz=48, T=T, wet_mode=mode, wet_value=value, omega=WALL_OMEGA, solid=mask,
+                   check_every=2000)
+    rl, rv = sim.rho_l, sim.rho_v
+    rho = inputs.sphere(shape, (48.0, 48.0, top + 17.0), 18.0, rl, rv)
+    rho[mask.astype(bool)] = rv
+    sim.init_density(torch.tensor(rho))
+    m0 = sim.reduce()[0]
+    sim.step(10000)
+    r = sim.fields()["rho"].cpu().numpy()
+    fluid = mask == 0
+    gap = np.zeros(shape, bool)
+    gap[plate:top, 36:60, 36:60] = True  # the texture below the droplet
+    gap &= fluid
+    liq = (r > 0.5 * (rl + rv)) & fluid
+    frac = float((liq & gap).sum() / gap.sum())
+    zc = float((np.arange(48)[:, None, None] * liq).sum() / liq.sum())
+    drift = abs(sim.reduce()[0] - m0) / m0
+    say(f"pillars {label}: liquid fraction of the gaps {frac:.3f}, liquid centre z {zc:.2f} (pillar tops {top}), "
+        f"mass drift {drift:.1e}")
+    if label == "hydrophobic":
+        assert frac < 0.01 and zc > top + 14
+    else:
+        assert frac > 0.2 and zc < top + 8
+    assert drift < 1e-10
