@@ -20,7 +20,11 @@ def check_state(sim, f_state, label):
     sim.set_populations(f_state)
     g = gpu_fields(sim)
     o = oracle_fields(f_state, p)
-    errs = {k: rel_err(g[k], o[k]) for k in o}
+    # a field that vanishes identically (F and Q on a one-node periodic box,
+    # where every link returns to the node) holds rounding residue on both
+    # sides: compare it absolutely
+    errs = {k: rel_err(g[k], o[k]) if float(o[k].abs().max()) > 1e-14 else float((g[k] - o[k]).abs().max())
+            for k in o}
     sim.step(1)
     fg = sim.populations().cpu()
     fo = lbm.step(f_state, p)
@@ -43,6 +47,11 @@ CASES = [
     ("walls drho 1.8", (12, 9, 7), True, dict(wet_mode=2, wet_value=1.8)),
     ("moving walls phi 1.4", (12, 9, 7), True, dict(wet_mode=1, wet_value=1.4, wall_u=(0.08, -0.03, -0.05, 0.02))),
     ("moving walls, one fluid plane", (3, 9, 7), True, dict(wall_u=(0.1, 0.0, -0.1, 0.05))),
+    # degenerate boxes: a periodic extent of 1 wraps every link onto the node itself
+    ("single z-plane 1x7x9", (1, 7, 9), False, {}),
+    ("single y-row 6x1x5", (6, 1, 5), False, {}),
+    ("single x-column 5x6x1", (5, 6, 1), False, {}),
+    ("single node 1x1x1", (1, 1, 1), False, {}),
 ]
 
 
@@ -81,7 +90,11 @@ def test_trajectory_stationary_droplet_32():
     f = lbm.run(f, p, steps)
     g = gpu_fields(sim)
     o = oracle_fields(f, p)
-    errs = {k: rel_err(g[k], o[k]) for k in o}
+    # a field that vanishes identically (F and Q on a one-node periodic box,
+    # where every link returns to the node) holds rounding residue on both
+    # sides: compare it absolutely
+    errs = {k: rel_err(g[k], o[k]) if float(o[k].abs().max()) > 1e-14 else float((g[k] - o[k]).abs().max())
+            for k in o}
     errs["f"] = rel_err(sim.populations().cpu(), f)
     say("droplet32 t=60: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     for k, v in errs.items():
@@ -102,7 +115,11 @@ def test_trajectory_sessile_droplet_walls():
     e = rel_err(fg[:, 1:-1], f[:, 1:-1])
     g = gpu_fields(sim)
     o = oracle_fields(f, p)
-    errs = {k: rel_err(g[k], o[k]) for k in o}
+    # a field that vanishes identically (F and Q on a one-node periodic box,
+    # where every link returns to the node) holds rounding residue on both
+    # sides: compare it absolutely
+    errs = {k: rel_err(g[k], o[k]) if float(o[k].abs().max()) > 1e-14 else float((g[k] - o[k]).abs().max())
+            for k in o}
     say(f"sessile t=30: f={e:.2e} " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     assert e < TOL and all(v < TOL for v in errs.values())
 
@@ -125,7 +142,11 @@ def test_trajectory_moving_walls():
     e = rel_err(fg[:, 1:-1], f[:, 1:-1])
     g = gpu_fields(sim)
     o = oracle_fields(f, p)
-    errs = {k: rel_err(g[k], o[k]) for k in o}
+    # a field that vanishes identically (F and Q on a one-node periodic box,
+    # where every link returns to the node) holds rounding residue on both
+    # sides: compare it absolutely
+    errs = {k: rel_err(g[k], o[k]) if float(o[k].abs().max()) > 1e-14 else float((g[k] - o[k]).abs().max())
+            for k in o}
     say(f"moving walls t=30: f={e:.2e} " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
     assert e < TOL and all(v < TOL for v in errs.values())
 
@@ -316,3 +337,13 @@ def test_state_roundtrip_and_counter():
     sim.step(4)
     assert sim.step_count == 7
     assert torch.equal(sim.get_state(), s7)
+
+
+def test_zero_steps_change_nothing():
+    T = eos.temperature(0.85)
+    sim = make_sim(nx=9, ny=8, nz=7, T=T)
+    sim.init_density(torch.tensor(droplet_rho((7, 8, 9), T)))
+    s0 = sim.get_state().clone()
+    sim.step(0)
+    assert torch.equal(sim.get_state(), s0)
+    assert sim.step_count == 0
