@@ -185,6 +185,63 @@ def time_adjoint(lbfe, torch, steps=20, form="fp32"):
     return out
 
 
+def spinodal_stats(lbfe, torch, steps=20000, chunk=500,
+                   forms=("fp64", "fp32", "fp16dev_f0fp32", "fp16dev")):
+    """Precision forms on the 256^3 spinodal workload, all run side by side
+    from the same initial density: the step at which max|rho - rho_FP64|
+    first exceeds 1e-2 (rho_l - rho_v) (checked every `chunk` steps), and at
+    the end, per form, the liquid volume fraction, the peak of the spherically
+    averaged structure factor (wavenumber index k* and wavelength 256/k*),
+    and the two peaks of the density histogram against the Maxwell pair."""
+    geom, rho, u, desc = workload("spinodal", lbfe, torch)
+    sims = {f: lbfe.Simulation(device="cuda:0", precision=f, check_every=chunk, **geom) for f in forms}
+    for sim in sims.values():
+        sim.init_density(torch.tensor(rho))
+    ref = sims[forms[0]]
+    rl, rv = ref.rho_l, ref.rho_v
+    cross = {f: None for f in forms[1:]}
+    t = 0
+    while t < steps:
+        for sim in sims.values():
+            sim.step(chunk)
+        t += chunk
+        r0 = ref.fields()["rho"]
+        for f in cross:
+            if cross[f] is None:
+                e = float((sims[f].fields()["rho"] - r0).abs().max()) / (rl - rv)
+                if e > 1e-2:
+                    cross[f] = t
+        if t % 2000 == 0:
+            print(f"[bench] spinodal statistics: step {t}", file=sys.stderr, flush=True)
+    n = geom["nx"]
+    k = torch.fft.fftfreq(n, d=1.0 / n, device="cuda:0").double()
+    kr = torch.fft.rfftfreq(n, d=1.0 / n, device="cuda:0").double()
+    kk = torch.sqrt(k[:, None, None] ** 2 + k[None, :, None] ** 2 + kr[None, None, :] ** 2)
+    shell = torch.round(kk).long().flatten()
+    out = {"workload": desc + ", precision forms side by side", "steps": steps, "check_every": chunk,
+           "rho_l": rl, "rho_v": rv, "forms": {}}
+    mid = 0.5 * (rl + rv)
+    for f, sim in sims.items():
+        r = sim.fields()["rho"]
+        P = torch.fft.rfftn(r - r.mean()).abs() ** 2
+        sk = torch.zeros(int(shell.max()) + 1, dtype=torch.float64, device="cuda:0").index_add_(0, shell, P.flatten())
+        cnt = torch.zeros_like(sk).index_add_(0, shell, torch.ones_like(P.flatten()))
+        sk = sk / cnt.clamp(min=1)
+        kpk = int(torch.argmax(sk[1:n // 2]).item()) + 1
+        hist = torch.histc(r.float(), bins=800, min=0.0, max=float(1.2 * rl))
+        centres = (torch.arange(800, device="cuda:0").double() + 0.5) * (1.2 * rl / 800)
+        lo_mask, hi_mask = centres < mid, centres >= mid
+        pk_v = float(centres[lo_mask][torch.argmax(hist[lo_mask])])
+        pk_l = float(centres[hi_mask][torch.argmax(hist[hi_mask])])
+        out["forms"][f] = {"liquid_fraction": float((r > mid).double().mean()), "k_peak": kpk,
+                           "wavelength": n / kpk, "hist_peak_vapour": pk_v, "hist_peak_liquid": pk_l,
+                           "step_pointwise_error_above_1e-2": cross.get(f)}
+    for sim in sims.values():
+        sim.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_collision_adjoint(lbfe, torch, forward=5000, adjoint=500, snapshots=8):
     """512^3 head-on collision in FP32: `forward` steps, then the adjoint of
     the last `adjoint` steps from the stored state f(T - adjoint) with the
@@ -324,6 +381,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=20)
     ap.add_argument("--collision-adjoint", nargs=3, type=int, metavar=("FORWARD", "ADJOINT", "SNAPSHOTS"),
                     help="time the 512^3 collision with a binomial-checkpointed adjoint of its last steps")
+    ap.add_argument("--spinodal-stats", nargs=2, type=int, metavar=("STEPS", "CHECK_EVERY"),
+                    help="256^3 spinodal in every storage form side by side: error onset and end statistics")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, form=args.forms.split(",")[0], workload_name=args.workload,
@@ -339,6 +398,9 @@ def main():
     if not torch.cuda.is_available():
         sys.stderr.write("bench.py needs a GPU\n")
         sys.exit(1)
+    if args.spinodal_stats:
+        print(json.dumps(spinodal_stats(lbfe, torch, *args.spinodal_stats)), flush=True)
+        return
     if args.collision_adjoint:
         print(json.dumps(time_collision_adjoint(lbfe, torch, *args.collision_adjoint)), flush=True)
         return
