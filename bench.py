@@ -242,6 +242,82 @@ def spinodal_stats(lbfe, torch, steps=20000, chunk=500,
     return out
 
 
+def wetting_adjoint(lbfe, torch, steps=4000, every=200, neutral=0, phi=1.3):
+    """The wetting workload's gradients at full size: 192x192x96, walls,
+    phi wetting, omega3 = 1/2, 0.7 T_c, `steps` steps.  Loss L = sum over
+    fluid nodes of (rho_T - rho_tgt)^2 with rho_tgt the final density of a
+    run at phi + 0.05 plus seeded noise of 1e-3 (rho_l - rho_v).  dL/dkappa,
+    dL/dphi and dL/drho0 at three nodes (liquid, interface, vapour) from the
+    hand-written adjoint (uniform checkpoints every `every` steps, FP32 and
+    FP64), against central differences of the FP64 forward.  neutral = 1:
+    the same with neutral wetting (no contact-line window, so the step is
+    smooth in the state), dL/dkappa and dL/drho0 only."""
+    from paper_2504_03819_amd import autograd as lag, inputs
+    geom, rho, u, desc = workload("wetting", lbfe, torch)
+    T, om = geom["T"], geom["omega"]
+    rl, rv = lbfe.coexistence(9 / 392, 2 / 21, 1.0, T)
+    kappa = 0.02
+    dev = "cuda:0"
+    mode = lbfe.WET_NEUTRAL if neutral else lbfe.WET_PHI
+
+    def forward64(k=kappa, w=phi, r0=None):
+        sim = lbfe.Simulation(device=dev, nx=192, ny=192, nz=96, T=T, walls_z=1, wet_mode=mode,
+                              wet_value=w, kappa=k, omega=om, check_every=steps)
+        sim.init_density(torch.tensor(rho if r0 is None else r0))
+        sim.step(steps)
+        out = sim.fields()["rho"]
+        sim.close()
+        return out
+
+    tgt = forward64(k=kappa * 1.05 if neutral else kappa, w=phi if neutral else phi + 0.05) + torch.tensor(1e-3 * (rl - rv) * inputs.uniform_noise(rho.shape, 1.0, 21),
+                                                  device=dev)
+
+    def loss(rT):
+        return ((rT - tgt)[1:-1] ** 2).sum()
+
+    nodes = [(48, 96, 96), (33, 96, 96), (80, 96, 96)]  # (z, y, x): liquid, near the interface, vapour
+    res = {"workload": desc + f", {steps} steps, " + ("neutral wetting, loss against a kappa x 1.05 run plus noise"
+                                                       if neutral else "loss against a phi + 0.05 run plus noise"),
+           "phi": phi,
+           "checkpoint_every": every, "nodes_zyx": nodes}
+    for form in ("fp32", "fp64"):
+        cfg = lag.StepConfig(nx=192, ny=192, nz=96, steps=steps, checkpoint_every=every, T=T, walls_z=1,
+                             wet_mode=mode, precision=form, omega=om, device=dev,
+                             keep_aux=form == "fp32")  # the FP64 segment without records fits in HBM
+        r0 = torch.tensor(rho, device=dev, requires_grad=True)
+        kap = torch.tensor(kappa, dtype=torch.float64, requires_grad=True)
+        wet = torch.tensor(phi, dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        L = loss(lag.simulate(r0, kap, wet, cfg))
+        L.backward()
+        torch.cuda.synchronize()
+        res[form] = {"loss": float(L), "dL_dkappa": float(kap.grad), "dL_dphi": float(wet.grad),
+                     "dL_drho0": [float(r0.grad[z, y, x]) for z, y, x in nodes], "seconds": time.time() - t0}
+        del r0, L
+        torch.cuda.empty_cache()
+        print(f"[bench] wetting adjoint {form} done", file=sys.stderr, flush=True)
+    hk, hp, hr = 2e-6, 1e-4, 1e-4
+    fd = {"dL_dkappa": (float(loss(forward64(k=kappa + hk))) - float(loss(forward64(k=kappa - hk)))) / (2 * hk),
+          "dL_dphi": 0.0 if neutral else
+          (float(loss(forward64(w=phi + hp))) - float(loss(forward64(w=phi - hp)))) / (2 * hp)}
+    d0 = []
+    for z, y, x in nodes:
+        rp, rm = rho.copy(), rho.copy()
+        rp[z, y, x] += hr
+        rm[z, y, x] -= hr
+        d0.append((float(loss(forward64(r0=rp))) - float(loss(forward64(r0=rm)))) / (2 * hr))
+    fd["dL_drho0"] = d0
+    res["central_differences_fp64"] = fd
+    for form in ("fp32", "fp64"):
+        g = res[form]
+        res[form]["rel_err_vs_fd"] = {
+            "kappa": abs(g["dL_dkappa"] - fd["dL_dkappa"]) / abs(fd["dL_dkappa"]),
+            "phi": abs(g["dL_dphi"] - fd["dL_dphi"]) / abs(fd["dL_dphi"]) if fd["dL_dphi"] else None,
+            "rho0": [abs(a - b) / abs(b) for a, b in zip(g["dL_drho0"], d0)]}
+    return res
+
+
 def time_collision_adjoint(lbfe, torch, forward=5000, adjoint=500, snapshots=8):
     """512^3 head-on collision in FP32: `forward` steps, then the adjoint of
     the last `adjoint` steps from the stored state f(T - adjoint) with the
@@ -381,6 +457,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=20)
     ap.add_argument("--collision-adjoint", nargs=3, type=int, metavar=("FORWARD", "ADJOINT", "SNAPSHOTS"),
                     help="time the 512^3 collision with a binomial-checkpointed adjoint of its last steps")
+    ap.add_argument("--wetting-adjoint", nargs=3, type=int, metavar=("STEPS", "CHECKPOINT_EVERY", "NEUTRAL"),
+                    help="192x192x96 wetting gradients (FP32 and FP64 adjoint) against central differences")
     ap.add_argument("--spinodal-stats", nargs=2, type=int, metavar=("STEPS", "CHECK_EVERY"),
                     help="256^3 spinodal in every storage form side by side: error onset and end statistics")
     args = ap.parse_args()
@@ -398,6 +476,9 @@ def main():
     if not torch.cuda.is_available():
         sys.stderr.write("bench.py needs a GPU\n")
         sys.exit(1)
+    if args.wetting_adjoint:
+        print(json.dumps(wetting_adjoint(lbfe, torch, *args.wetting_adjoint)), flush=True)
+        return
     if args.spinodal_stats:
         print(json.dumps(spinodal_stats(lbfe, torch, *args.spinodal_stats)), flush=True)
         return
