@@ -16,7 +16,9 @@
  *    i = 9 (cx+1) + 3 (cy+1) + (cz+1), rest i = 13, opposite 26 - i.
  *  - With walls_z = 1 the planes z = 0 and z = nz-1 are solid (halfway
  *    bounce-back and the wetting boundary of Sec. III C); every other node is
- *    fluid.  With walls_z = 0 the box is periodic in all three directions.
+ *    fluid.  With walls_z = 0 the box is periodic in all three directions,
+ *    and with solid_mask = 1 the solid nodes are those of a voxel mask
+ *    (lbfe_set_solid) in that periodic box.
  *  - Pointers named *_dev are device pointers (HIP device memory on the
  *    context's device); all others are host pointers.  Every buffer is owned
  *    by the caller; the library never allocates or frees device memory: it
@@ -115,7 +117,10 @@ int lbfe_coexistence(double a, double b, double R, double T, double *rho_l, doub
  * to the current HIP device and the given stream (hipStream_t as void*;
  * NULL = default stream).  Allocates no device memory.
  * E_INVAL on a bad parameter (checked before any device call), E_DEVICE
- * when no GPU is usable. */
+ * when no GPU is usable.  The tile order of the streaming kernels (one
+ * contiguous range of tiles per XCD, on from 2^26 nodes) can be forced with
+ * the environment variable LBFE_XCD_REMAP=0/1, read here; it changes the
+ * schedule only, never the result. */
 int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out);
 
 /* Bytes of device workspace a context with these parameters needs. */
