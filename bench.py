@@ -344,7 +344,7 @@ def time_collision_adjoint(lbfe, torch, forward=5000, adjoint=500, snapshots=8):
         sim.step(k)
         done += k
         print(f"[bench] collision forward step {done}", file=sys.stderr, flush=True)
-    state = sim.get_state().clone()
+    state = sim.get_state()
     sim.step(adjoint)
     e[1].record(sim.stream)
     rho_T = sim.fields()["rho"]

@@ -235,8 +235,10 @@ int lbfe_adjoint_seed_populations(lbfe_ctx *ctx, const double *dL_df_dev);
 int lbfe_adjoint_get(lbfe_ctx *ctx, double *lambda_dev);
 
 /* lambda(t) = (d step / d f(t))^T lambda(t+1), accumulating dL/dkappa,
- * dL/d(wet_value) and dL/dnu.  state_t_dev: f(t) at storage precision.
- * Overwrites the auxiliary fields of the context. */
+ * dL/d(wet_value) and dL/dnu.  state_t_dev: f(t) at storage precision, or
+ * NULL for the context's current state (e.g. f(t) just recomputed with
+ * lbfe_step, which saves copying it out; E_STATE if there is none).  The
+ * state is only read.  Overwrites the auxiliary fields of the context. */
 int lbfe_adjoint_step(lbfe_ctx *ctx, const void *state_t_dev);
 
 /* Forward auxiliary fields kept for the adjoint.  A checkpointed reverse

@@ -75,6 +75,13 @@ def reverse_binomial(sim, state_a, a, b, snapshots, stats=None):
     stats.setdefault("recompute_steps", 0)
     stats.setdefault("max_held", 0)
 
+    cur = [None]  # the stored state the simulation currently holds, if any
+
+    def load(st, lo):
+        if cur[0] is not st:
+            sim.set_state(st, lo)
+            cur[0] = st
+
     def rev(st, lo, hi, s, held):
         stats["max_held"] = max(stats["max_held"], held)
         t = hi - lo
@@ -86,20 +93,22 @@ def reverse_binomial(sim, state_a, a, b, snapshots, stats=None):
                 if k == lo:
                     sim.adjoint_step(st)
                 else:
-                    sim.set_state(st, lo)
+                    load(st, lo)
                     sim.step(k - lo)
+                    cur[0] = None
                     stats["recompute_steps"] += k - lo
-                    sim.adjoint_step(sim.get_state().clone())
+                    sim.adjoint_step(None)  # f(k) is the simulation's current state
             return
         r = 1
         while comb(s + r, s) < t:
             r += 1
         m = min(t - 1, comb(s + r - 1, s))
         m = max(m, t - comb(s - 1 + r, s - 1), 1)
-        sim.set_state(st, lo)
+        load(st, lo)
         sim.step(m)
         stats["recompute_steps"] += m
-        st_m = sim.get_state().clone()
+        st_m = sim.get_state()
+        cur[0] = st_m  # (an adjoint step only reads the state)
         rev(st_m, lo + m, hi, s - 1, held + 1)
         del st_m
         rev(st, lo, lo + m, s, held)
@@ -116,11 +125,11 @@ class LBFEFunction(torch.autograd.Function):
         K = max(1, int(cfg.checkpoint_every))
         checkpoints = {}
         if cfg.checkpoint == "binomial":
-            checkpoints[0] = sim.get_state().clone()
+            checkpoints[0] = sim.get_state()
             sim.step(cfg.steps)
         else:
             for s in range(0, cfg.steps, K):
-                checkpoints[s] = sim.get_state().clone()
+                checkpoints[s] = sim.get_state()
                 sim.step(min(K, cfg.steps - s))
         rho_T = sim.fields()["rho"]
         ctx.sim, ctx.cfg, ctx.checkpoints = sim, cfg, checkpoints
@@ -140,19 +149,23 @@ class LBFEFunction(torch.autograd.Function):
             for s0 in sorted(ctx.checkpoints, reverse=True):
                 s1 = min(s0 + K, cfg.steps)
                 sim.set_state(ctx.checkpoints[s0], s0)
-                states = [sim.get_state().clone()]
-                recs = []
-                for _ in range(s0 + 1, s1):
+                # states[k] = f(s0 + k) for the states that are stepped from
+                # (with the record of their fields if kept); the segment's
+                # last state stays in the simulation
+                states, recs = [ctx.checkpoints[s0]], []
+                for t in range(s0, s1 - 1):
                     if cfg.keep_aux:
                         recs.append(sim.aux_record())
                         sim.step_aux(recs[-1])
                     else:
                         sim.step(1)
-                    states.append(sim.get_state().clone())
-                for t in range(s1 - 1, s0 - 1, -1):
-                    if t - s0 < len(recs):
+                    if t + 1 < s1 - 1:
+                        states.append(sim.get_state())
+                sim.adjoint_step(None)  # f(s1 - 1)
+                for t in range(s1 - 2, s0 - 1, -1):
+                    if cfg.keep_aux:
                         sim.adjoint_step_aux(states[t - s0], recs[t - s0])
-                    else:  # the segment's last state was never stepped from
+                    else:
                         sim.adjoint_step(states[t - s0])
                 del states, recs
         g_rho0 = sim.adjoint_init_density(rho0.detach(), cfg.u0)

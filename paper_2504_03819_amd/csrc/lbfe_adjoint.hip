@@ -23,25 +23,29 @@
 #include <type_traits>
 
 #include "lbfe_device.h"
+#include "lbfe_dpp.h"
 
 namespace lbfe {
 namespace {
 
 template <int P> using real_t = typename Pol<P>::real;
 
-// Adjoint auxiliary arrays (double, N each) inside Bufs::abuf.
+// Adjoint auxiliary arrays inside Bufs::abuf, in slots of N doubles.  The
+// slots marked (real) hold planes in the compute precision (three float
+// planes use half of their three slots): those values are formed in that
+// precision, so keeping them narrower loses nothing.
 enum : int {
-    A_UB = 0,    // 3: u_bar
-    A_FB = 3,    // 3: F_bar
-    A_QB = 6,    // 3: Q_bar (after folding the fourth-order terms)
+    A_UB = 0,    // 3 (real): u_bar
+    A_FB = 3,    // 3 (real): F_bar
+    A_QB = 6,    // 3 (real): Q_bar (after folding the fourth-order terms)
     A_PMB = 9,   // p_m bar
     A_RHOB = 10, // rho bar (local part)
-    A_JB = 11,   // 3: j bar
+    A_JB = 11,   // 3 (real): j bar, rounded to the compute precision
     A_GB = 14,   // 3: G bar (G = grad mu)
     A_MUB = 17,  // mu bar (all nodes)
     A_KAPC = 18, // per-node dL/dkappa contribution
     A_NUC = 19,  // per-node dL/dnu contribution
-    A_WETC = 20, // per-solid-node dL/d(wet) contribution
+    A_WETC = 20, // dL/d(wet) contribution per wall node, 2 planes packed
     A_RAVEB = 21,// rho_ave bar at solid nodes
     A_RHOBT = 22,// rho bar total (all nodes)
     A_MUBT = 23, // mu bar total (all nodes)
@@ -59,6 +63,11 @@ template <class real> struct Lam {
     __device__ real ld(int i, unsigned row, unsigned x) const { return p[off(i, row, x)]; }
     __device__ void st(int i, unsigned row, unsigned x, real v) const { p[off(i, row, x)] = v; }
 };
+
+// Plane c of a (real) slot group.
+template <class real> __device__ inline real *aplane(void *abuf, int slot, int c, size_t N) {
+    return (real *)((double *)abuf + (size_t)slot * N) + (size_t)c * N;
+}
 
 // ---- transposed 1-D transforms -------------------------------------------
 // Transpose of the inverse map (k0,k1,k2) -> (f-,f0,f+) (see inv3).
@@ -233,10 +242,6 @@ template <class real> __device__ inline real final_term(real rb, real jx, real j
     if (czi(i)) add += (real)czi(i) * jz;
     return add;
 }
-template <class real> __device__ inline real final_term(const double *A, size_t N, int i, size_t m) {
-    return final_term<real>((real)A[A_RHOBT * N + m], (real)A[A_JB * N + m], (real)A[(A_JB + 1) * N + m],
-                            (real)A[(A_JB + 2) * N + m], i);
-}
 // the same four values packed per node (k_adj_pack), one vector load
 template <class real> using Pack4 = std::conditional_t<std::is_same_v<real, double>, double4, float4>;
 template <class real> __device__ inline real final_term(const Pack4<real> *pk, int i, size_t m) {
@@ -244,19 +249,21 @@ template <class real> __device__ inline real final_term(const Pack4<real> *pk, i
     return final_term<real>(t.x, t.y, t.z, t.w, i);
 }
 
+template <class real> __device__ inline void store_pack(void *abuf, size_t N, size_t n, double rhobt) {
+    Pack4<real> t;
+    t.x = (real)rhobt;
+    t.y = aplane<real>(abuf, A_JB, 0, N)[n];
+    t.z = aplane<real>(abuf, A_JB, 1, N)[n];
+    t.w = aplane<real>(abuf, A_JB, 2, N)[n];
+    ((Pack4<real> *)((double *)abuf + A_PACK * N))[n] = t;
+}
+
 template <int P> __global__ __launch_bounds__(kBlock) void k_adj_pack(KP kp, Bufs b) {
     using real = real_t<P>;
     const unsigned idx = tile_id(kp) * kBlock + threadIdx.x;
     if (idx >= kp.nfluid) return;
     const size_t n = (size_t)kp.z0 * kp.plane + idx, N = kp.N;
-    const double *A = (const double *)b.abuf;
-    Pack4<real> *pk = (Pack4<real> *)(A + A_PACK * N);
-    Pack4<real> t;
-    t.x = (real)A[A_RHOBT * N + n];
-    t.y = (real)A[A_JB * N + n];
-    t.z = (real)A[(A_JB + 1) * N + n];
-    t.w = (real)A[(A_JB + 2) * N + n];
-    pk[n] = t;
+    store_pack<real>(b.abuf, N, n, ((const double *)b.abuf)[A_RHOBT * N + n]);
 }
 
 // ---------------------------------------------------------------------------
@@ -316,16 +323,41 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     const bool wall_lo = kp.walls && z == 1;
     const bool wall_hi = kp.walls && z == kp.nz - 2;
     real l[27];
-    const Pack4<real> *pk = (const Pack4<real> *)((const double *)b.abuf + A_PACK * (size_t)kp.N);
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int cz = czi(i);
-        if ((cz < 0 && wall_lo) || (cz > 0 && wall_hi)) {
+        if ((cz < 0 && wall_lo) || (cz > 0 && wall_hi))
             l[i] = lin.ld(26 - i, row, (unsigned)x);
-            if constexpr (PEND) l[i] += final_term<real>(pk, 26 - i, n);
-        } else {
+        else
             l[i] = lin.ld(i, nb.row(cyi(i), cz), nb.xo(cxi(i)));
-            if constexpr (PEND) l[i] += final_term<real>(pk, i, nb.at(cxi(i), cyi(i), cz));
+    }
+    if constexpr (PEND) {
+        // The pending (rho_bar_total, j_bar) of the 27 neighbours, one row
+        // (cy, cz) at a time: the x - 1 and x + 1 values are those of the
+        // adjacent lanes (a wave holds consecutive nodes), loaded only by
+        // the lanes at a wave's or a row's ends.  The last active lane of
+        // a partial wave has x = nx - 1 (fluid rows are whole).
+        const Pack4<real> *pk = (const Pack4<real> *)((const double *)b.abuf + A_PACK * (size_t)kp.N);
+        const unsigned lane = threadIdx.x & 63u;
+        const bool own_m = lane == 0u || x == 0, own_p = lane == 63u || x == kp.nx - 1;
+        const Pack4<real> c0 = pk[n];
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            const int cy = r / 3 - 1, cz = r % 3 - 1;
+            const Pack4<real> c = pk[nb.at(0, cy, cz)];
+            Pack4<real> m, p;
+            m.x = shr1(c.x), m.y = shr1(c.y), m.z = shr1(c.z), m.w = shr1(c.w);
+            p.x = shl1(c.x), p.y = shl1(c.y), p.z = shl1(c.z), p.w = shl1(c.w);
+            if (own_m) m = pk[nb.at(-1, cy, cz)];
+            if (own_p) p = pk[nb.at(1, cy, cz)];
+            const bool bb = (cz < 0 && wall_lo) || (cz > 0 && wall_hi);
+#pragma unroll
+            for (int cx = -1; cx <= 1; ++cx) {
+                const int i = 9 * (cx + 1) + 3 * (cy + 1) + (cz + 1);
+                const Pack4<real> t = cx < 0 ? m : (cx > 0 ? p : c);
+                l[i] += bb ? final_term<real>(c0.x, c0.y, c0.z, c0.w, 26 - i)
+                           : final_term<real>(t.x, t.y, t.z, t.w, i);
+            }
         }
     }
     cm_inverse_T(l, ux, uy, uz);  // l = lambda_hat (adjoint of k*)
@@ -357,15 +389,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     const double nub = -om1b * o * o * rr / dpm;
     const size_t N = kp.N;
     double *A = (double *)b.abuf;
-    A[(A_UB + 0) * N + n] = (double)ubx;
-    A[(A_UB + 1) * N + n] = (double)uby;
-    A[(A_UB + 2) * N + n] = (double)ubz;
-    A[(A_FB + 0) * N + n] = (double)sb.F[0];
-    A[(A_FB + 1) * N + n] = (double)sb.F[1];
-    A[(A_FB + 2) * N + n] = (double)sb.F[2];
-    A[(A_QB + 0) * N + n] = (double)qb0;
-    A[(A_QB + 1) * N + n] = (double)qb1;
-    A[(A_QB + 2) * N + n] = (double)qb2;
+    aplane<real>(A, A_UB, 0, N)[n] = ubx;
+    aplane<real>(A, A_UB, 1, N)[n] = uby;
+    aplane<real>(A, A_UB, 2, N)[n] = ubz;
+    aplane<real>(A, A_FB, 0, N)[n] = sb.F[0];
+    aplane<real>(A, A_FB, 1, N)[n] = sb.F[1];
+    aplane<real>(A, A_FB, 2, N)[n] = sb.F[2];
+    aplane<real>(A, A_QB, 0, N)[n] = qb0;
+    aplane<real>(A, A_QB, 1, N)[n] = qb1;
+    aplane<real>(A, A_QB, 2, N)[n] = qb2;
     A[A_PMB * N + n] = pmb;
     A[A_RHOB * N + n] = rhob;
     A[A_NUC * N + n] = nub;
@@ -391,6 +423,8 @@ __device__ inline int zwrap(int v, int n) {
 template <int NF> struct ZRing {
     double (*lds)[NF][ZNR];  // [4][NF][ZNR]
     const double *src[NF];
+    const float *srcf[NF];  // field f is read from here instead when bit f of fmask is set
+    unsigned fmask;
     int a, b, tid, nz;
     bool own;       // the tile point is inside the grid
     unsigned node;  // its in-plane index
@@ -412,6 +446,7 @@ template <int NF> struct ZRing {
         own = x0 + a < k.nx && y0 + b < k.ny;
         node = own ? (unsigned)(y0 + b) * k.nx + (x0 + a) : 0u;
         zmask = 0;
+        fmask = 0;
 #pragma unroll
         for (int m = 0; m < ZM; ++m) {
             const int r = tid + m * ZCB;
@@ -428,7 +463,10 @@ template <int NF> struct ZRing {
         for (int f = 0; f < NF; ++f)
 #pragma unroll
             for (int m = 0; m < ZM; ++m)
-                if (has[m]) pre[f][m] = ((zmask >> f) & 1) && !fl ? 0.0 : src[f][base + off[m]];
+                if (has[m])
+                    pre[f][m] = ((zmask >> f) & 1) && !fl ? 0.0
+                                : ((fmask >> f) & 1)     ? (double)srcf[f][base + off[m]]
+                                                         : src[f][base + off[m]];
     }
     __device__ void commit(int p) {
 #pragma unroll
@@ -475,9 +513,14 @@ template <int P> __global__ __launch_bounds__(ZCB) void k_adj_phi(KP kp, Bufs b,
     double *A = (double *)b.abuf;
     ZRing<4> R;
     R.init(kp, lds, x0, y0);
-    R.src[0] = A + A_QB * N;
-    R.src[1] = A + (A_QB + 1) * N;
-    R.src[2] = A + (A_QB + 2) * N;
+    for (int c = 0; c < 3; ++c) {
+        if constexpr (std::is_same_v<real, float>) {
+            R.srcf[c] = aplane<float>(A, A_QB, c, N);
+            R.fmask |= 1u << c;
+        } else {
+            R.src[c] = aplane<double>(A, A_QB, c, N);
+        }
+    }
     R.src[3] = b.mu;
     const real *j = (const real *)b.j, *F = (const real *)b.F;
     R.march(zs, ze, [&](int k) {
@@ -508,16 +551,16 @@ template <int P> __global__ __launch_bounds__(ZCB) void k_adj_phi(KP kp, Bufs b,
         const double pu = px * ux + py * uy + pz * uz;
         pmb += pu;
         rhob -= pu / 3.0;
-        const double utx = A[A_UB * N + n] + c2 * px;
-        const double uty = A[(A_UB + 1) * N + n] + c2 * py;
-        const double utz = A[(A_UB + 2) * N + n] + c2 * pz;
-        // u = (j + F/2)/rho
-        A[A_JB * N + n] = utx / r;
-        A[(A_JB + 1) * N + n] = uty / r;
-        A[(A_JB + 2) * N + n] = utz / r;
-        const double Fbx = A[A_FB * N + n] + 0.5 * utx / r;
-        const double Fby = A[(A_FB + 1) * N + n] + 0.5 * uty / r;
-        const double Fbz = A[(A_FB + 2) * N + n] + 0.5 * utz / r;
+        const double utx = (double)aplane<real>(A, A_UB, 0, N)[n] + c2 * px;
+        const double uty = (double)aplane<real>(A, A_UB, 1, N)[n] + c2 * py;
+        const double utz = (double)aplane<real>(A, A_UB, 2, N)[n] + c2 * pz;
+        // u = (j + F/2)/rho; j_bar is only used in the compute precision
+        aplane<real>(A, A_JB, 0, N)[n] = (real)(utx / r);
+        aplane<real>(A, A_JB, 1, N)[n] = (real)(uty / r);
+        aplane<real>(A, A_JB, 2, N)[n] = (real)(utz / r);
+        const double Fbx = (double)aplane<real>(A, A_FB, 0, N)[n] + 0.5 * utx / r;
+        const double Fby = (double)aplane<real>(A, A_FB, 1, N)[n] + 0.5 * uty / r;
+        const double Fbz = (double)aplane<real>(A, A_FB, 2, N)[n] + 0.5 * utz / r;
         rhob -= (utx * ux + uty * uy + utz * uz) / r;
         // F = (1/3 - rho) G, G = grad_h mu recomputed
         double gx = 0.0, gy = 0.0, gz = 0.0;
@@ -687,7 +730,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_wall_rho_solid(KP kp, const doub
         }
     }
     raveb[n] = dW * g;
-    wetc[n] = dwet * g;
+    wetc[idx] = dwet * g;
 }
 
 // lambda_i(t) = direct part + rho_bar_total + c_i . j_bar at fluid nodes.
@@ -697,26 +740,26 @@ template <int P> __global__ __launch_bounds__(kBlock) void k_adj_final(KP kp, Bu
     if (idx >= kp.nfluid) return;
     const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
     const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
-    const size_t N = kp.N;
-    const double *A = (const double *)b.abuf;
+    const Pack4<real> *pk = (const Pack4<real> *)((const double *)b.abuf + A_PACK * (size_t)kp.N);
     const Lam<real> L(lam, kp);
 #pragma unroll
-    for (int i = 0; i < 27; ++i) L.st(i, row, x, L.ld(i, row, x) + final_term<real>(A, N, i, n));
+    for (int i = 0; i < 27; ++i) L.st(i, row, x, L.ld(i, row, x) + final_term<real>(pk, i, n));
 }
 
-// Deterministic accumulation: per-block sums of three per-node arrays, then
-// one block adds them (fixed order) to acc[0..2].
-__global__ __launch_bounds__(kBlock) void k_adj_reduce_part(unsigned n, const double *a0, const double *a1,
-                                                            const double *a2, double *part) {
+// Deterministic accumulation: per-block sums of three arrays (a0, a2 of n
+// entries, a1 of n1), then one block adds them (fixed order) to acc[0..2].
+__global__ __launch_bounds__(kBlock) void k_adj_reduce_part(unsigned n, const double *a0, unsigned n1,
+                                                            const double *a1, const double *a2, double *part) {
     __shared__ double s[3][kBlock];
     // a fixed grid-stride assignment: the same sums in the same order on
     // every call
     double v0 = 0.0, v1 = 0.0, v2 = 0.0;
     for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         if (a0) v0 += a0[i];
-        if (a1) v1 += a1[i];
         if (a2) v2 += a2[i];
     }
+    if (a1)
+        for (unsigned i = blockIdx.x * kBlock + threadIdx.x; i < n1; i += gridDim.x * kBlock) v1 += a1[i];
     s[0][threadIdx.x] = v0;
     s[1][threadIdx.x] = v1;
     s[2][threadIdx.x] = v2;
@@ -870,7 +913,8 @@ hipError_t chain_tail(hipStream_t s, const KP &kp, const Bufs &b, bool with_grad
     }
     double *part = b.agrad + 8;
     const unsigned gr = gN < kReduceBlocks ? gN : kReduceBlocks;
-    k_adj_reduce_part<<<gr, kBlock, 0, s>>>((unsigned)N, A + A_KAPC * N, wetc, nuc, part);
+    k_adj_reduce_part<<<gr, kBlock, 0, s>>>((unsigned)N, A + A_KAPC * N, 2u * (unsigned)kp.plane, wetc, nuc,
+                                            part);
     k_adj_reduce_final<<<1, kBlock, 0, s>>>(gr, part, b.agrad);
     return hipGetLastError();
 }

@@ -634,7 +634,10 @@ int lbfe_adjoint_step(lbfe_ctx *c, const void *ft) {
     if (r) return r;
     if (!c->p.adjoint) return fail(c, LBFE_E_STATE, "created without params.adjoint = 1");
     if (!c->adj_seeded) return fail(c, LBFE_E_STATE, "adjoint not seeded");
-    if (!ft) return fail(c, LBFE_E_INVAL, "null state");
+    if (!ft) {  // the context's current state (read only: the step writes lambda and fields)
+        if (!c->initialised) return fail(c, LBFE_E_STATE, "no current state");
+        ft = c->b.f[c->cur];
+    }
     c->aux_ok = false;  // the recomputation below overwrites rho, j, mu0
     hipError_t e = launch_adj_step(c->stream, c->p.precision, c->kp, c->b, c->lcur, ft, true, c->lam_pending);
     if (e != hipSuccess) return hip_fail(c, e, "adjoint_step");

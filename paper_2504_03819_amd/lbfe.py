@@ -276,7 +276,8 @@ class Simulation:
         self._check(lib().lbfe_adjoint_get(self._ctx, _ptr(out)))
         return out
 
-    def adjoint_step(self, state_t):
+    def adjoint_step(self, state_t=None):
+        """One adjoint step with f(t) = state_t, or the current state if None."""
         self._check(lib().lbfe_adjoint_step(self._ctx, _ptr(state_t)))
 
     # ------------------------------------- forward fields kept for the adjoint --

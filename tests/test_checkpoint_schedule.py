@@ -31,7 +31,8 @@ class _Recorder:
         return _S((self.t,))
 
     def adjoint_step(self, st):
-        self.seen.append(st[0])
+        # None: the adjoint step takes the simulation's current state
+        self.seen.append(self.t if st is None else st[0])
 
 
 def _bound(t, s):

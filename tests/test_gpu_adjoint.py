@@ -159,15 +159,16 @@ def test_end_to_end_gradients_vs_oracle_and_fd(walls, wet_mode, wet_value):
 
 def test_checkpoint_interval_does_not_change_gradients():
     """Uniform checkpoints every 1, 4, 9 steps (with and without the kept
-    forward fields) and the binomial schedule with two snapshots give
-    bitwise identical gradients."""
+    forward fields) and the binomial schedule with zero, one and two
+    snapshots give bitwise identical gradients."""
     shape = (10, 8, 8)
     rho0, tgt, cfg = _loss_setup(shape, True, 1, 1.3, 9)
     grads = []
-    for K, mode, keep in ((1, "uniform", True), (4, "uniform", True), (4, "uniform", False), (9, "uniform", True),
-                          (9, "uniform", False), (0, "binomial", False)):
+    for K, mode, keep, snaps in ((1, "uniform", True, 0), (4, "uniform", True, 0), (4, "uniform", False, 0),
+                                 (9, "uniform", True, 0), (9, "uniform", False, 0), (0, "binomial", False, 2),
+                                 (0, "binomial", False, 1), (0, "binomial", False, 0)):
         cfg.checkpoint_every = max(K, 1)
-        cfg.checkpoint, cfg.snapshots, cfg.keep_aux = mode, 2, keep
+        cfg.checkpoint, cfg.snapshots, cfg.keep_aux = mode, snaps, keep
         r0 = torch.tensor(rho0, device="cuda", requires_grad=True)
         kap = torch.tensor(0.02, dtype=DT, requires_grad=True)
         wet = torch.tensor(1.3, dtype=DT, requires_grad=True)
@@ -230,6 +231,40 @@ def test_adjoint_step_with_kept_aux_is_bitwise_the_same(form):
     with pytest.raises(lbfe.LBFEError) as e:
         b.adjoint_step_aux(states[0], bad[8:])
     assert e.value.code == lbfe.E_INVAL
+
+
+@pytest.mark.parametrize("form", ["fp64", "fp32"])
+def test_adjoint_step_from_the_current_state(form):
+    """lbfe_adjoint_step with a NULL state takes the context's current state:
+    a sweep that sets each f(t) in the context and steps from it there ends
+    with the lambda and gradients of a sweep over stored copies, bit for bit.
+    Without a current state the call is refused."""
+    shape = (10, 9, 11)
+    T = eos.temperature(0.7)
+    rho0 = droplet_rho(shape, T, walls=True, radius=3.5, noise=1e-2, seed=5)
+    kw = dict(nx=11, ny=9, nz=10, T=T, walls_z=1, wet_mode=1, wet_value=1.3, precision=form, adjoint=1)
+    a, b = make_sim(**kw), make_sim(**kw)
+    for s in (a, b):
+        s.init_density(torch.tensor(rho0))
+    states = []
+    for _ in range(5):
+        states.append(a.get_state())
+        a.step(1)
+    g = torch.tensor(inputs.uniform_noise(shape, 1.0, 9), device="cuda")
+    a.adjoint_seed(g)
+    b.adjoint_seed(g)
+    for t in range(4, -1, -1):
+        a.adjoint_step(states[t])
+        b.set_state(states[t], t)
+        b.adjoint_step(None)
+        assert torch.equal(b.get_state(), states[t])  # only read
+    assert torch.equal(a.adjoint_state().cpu(), b.adjoint_state().cpu())
+    assert a.adjoint_grads() == b.adjoint_grads()
+    c = make_sim(**kw)
+    c.adjoint_seed(g)
+    with pytest.raises(lbfe.LBFEError) as e:
+        c.adjoint_step(None)
+    assert e.value.code == lbfe.E_STATE
 
 
 def test_reading_lambda_mid_sweep_changes_nothing():
