@@ -8,8 +8,9 @@ line) and, as extra fields, in the FP32 and FP16-deviation storage forms.
 Prints ONE JSON line.  `value` is whole-job MLUPS (fluid nodes x steps /
 s / 1e6) of the FP64 form, measured with HIP events around K steps on the
 library's stream, inputs resident in HBM.  `roofline` describes the dominant
-kernel (collide-stream); `cpu_baseline` times the CPU oracle on a bounded
-sample of the same workload.
+kernel (collide-stream), with the bandwidth a plain 4 GiB device copy
+attains beside it; `cpu_baseline` times the CPU oracle on a bounded sample
+of the same workload.
 
     python bench.py [--gpus 1] [--steps 200] [--warmup 20]
 """
@@ -403,6 +404,29 @@ def copy_calibration(torch, gib=1):
     torch.cuda.empty_cache()
 
 
+def copy_bandwidth(torch, gib=4, reps=10):
+    """Attainable HBM bandwidth: a streaming copy of gib GiB through torch's
+    vectorised elementwise kernel (b = 1 * a; read + write bytes over the
+    mean time of `reps` copies, HIP events).  The runtime's own
+    device-to-device copy is slower on this GPU (4.6-5.2 TB/s against
+    6.0-6.2), so it is not used as the reference."""
+    n = gib * (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.mul(a, 1.0, out=b)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        torch.mul(a, 1.0, out=b)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * n * 4 / (ms / 1e3) / 1e9
+
+
 def _read_counter_csv(path, counter):
     """Per-kernel list of one counter's values (KiB per dispatch) from a
     rocprofv3 counter_collection.csv."""
@@ -522,6 +546,10 @@ def main():
             tb += sum(v * wf for k, v in c["kernels"]["write_kib"].items() if any(s in k for s in step_kernels))
             roof["step_traffic"] = tb * 1024.0
             roof["step_achieved_frac"] = round(tb * 1024.0 / (r["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    print("[bench] device copy bandwidth", file=sys.stderr, flush=True)
+    cbw = copy_bandwidth(torch)
+    roof["copy_GBps"] = round(cbw, 1)
+    roof["frac_of_copy"] = round(r["collide_alg_GBps"] / cbw, 4)
     adj = None
     if not args.no_adjoint:
         print("[bench] timing the adjoint (wetting workload, FP32)", file=sys.stderr, flush=True)
