@@ -323,21 +323,37 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     const bool wall_lo = kp.walls && z == 1;
     const bool wall_hi = kp.walls && z == kp.nz - 2;
     real l[27];
+    const Pack4<real> *pk = (const Pack4<real> *)((const double *)b.abuf + A_PACK * (size_t)kp.N);
+    if constexpr (PEND && sizeof(real) == 8) {
+        // FP64: the pending (rho_bar_total, j_bar) of each link's neighbour
+        // with one vector load per link, beside the link's lambda (the
+        // lane-shift form below needs more registers than an FP64 wave has
+        // at two waves per SIMD)
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const int cz = czi(i);
-        if ((cz < 0 && wall_lo) || (cz > 0 && wall_hi))
-            l[i] = lin.ld(26 - i, row, (unsigned)x);
-        else
-            l[i] = lin.ld(i, nb.row(cyi(i), cz), nb.xo(cxi(i)));
+        for (int i = 0; i < 27; ++i) {
+            const int cz = czi(i);
+            if ((cz < 0 && wall_lo) || (cz > 0 && wall_hi))
+                l[i] = lin.ld(26 - i, row, (unsigned)x) + final_term<real>(pk, 26 - i, n);
+            else
+                l[i] = lin.ld(i, nb.row(cyi(i), cz), nb.xo(cxi(i))) +
+                       final_term<real>(pk, i, nb.at(cxi(i), cyi(i), cz));
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const int cz = czi(i);
+            if ((cz < 0 && wall_lo) || (cz > 0 && wall_hi))
+                l[i] = lin.ld(26 - i, row, (unsigned)x);
+            else
+                l[i] = lin.ld(i, nb.row(cyi(i), cz), nb.xo(cxi(i)));
+        }
     }
-    if constexpr (PEND) {
+    if constexpr (PEND && sizeof(real) == 4) {
         // The pending (rho_bar_total, j_bar) of the 27 neighbours, one row
         // (cy, cz) at a time: the x - 1 and x + 1 values are those of the
         // adjacent lanes (a wave holds consecutive nodes), loaded only by
         // the lanes at a wave's or a row's ends.  The last active lane of
         // a partial wave has x = nx - 1 (fluid rows are whole).
-        const Pack4<real> *pk = (const Pack4<real> *)((const double *)b.abuf + A_PACK * (size_t)kp.N);
         const unsigned lane = threadIdx.x & 63u;
         const bool own_m = lane == 0u || x == 0, own_p = lane == 63u || x == kp.nx - 1;
         const Pack4<real> c0 = pk[n];
