@@ -368,23 +368,20 @@ __global__ __launch_bounds__(CB) void k_chain(KP kp, const double *__restrict__ 
 
 }  // namespace
 
-// Planes per workgroup: enough workgroups to fill the chip (>= ~2048),
-// otherwise as long as possible to amortise the six pipeline-fill planes.
-// Small grids, where even 8-plane chunks leave CUs idle, go below 8 planes
-// when that shortens the longest march: with one workgroup per CU that is
-// (rounds of workgroups) x (planes + 6 fill planes) iterations.
+// Planes per workgroup.  One workgroup fits a CU (LDS), and every march
+// starts with six pipeline-fill planes, so chunks of c planes cost the
+// busiest CU ceil(workgroups / CUs) x (c + 6) plane iterations; the chunk
+// length from 32 down to 1 that minimises it is taken (the longer on ties).
 constexpr unsigned kCUs = 256;  // MI355X
 static int chain_chunk(const KP &kp, unsigned tiles) {
     const int nzf = kp.z1 - kp.z0;
-    int cz = 32;
-    while (cz > 8 && (size_t)tiles * ((nzf + cz - 1) / cz) * CB < 2048 * 256) cz /= 2;
     auto iters = [&](int c) {
         const size_t wg = (size_t)tiles * ((nzf + c - 1) / c);
         return ((wg + kCUs - 1) / kCUs) * (size_t)(c + 6);
     };
-    if (cz == 8)
-        for (int c = 4; c >= 1; c /= 2)
-            if (iters(c) < iters(cz)) cz = c;
+    int cz = 32;
+    for (int c = 16; c >= 1; c /= 2)
+        if (iters(c) < iters(cz)) cz = c;
     return cz;
 }
 
