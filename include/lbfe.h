@@ -120,7 +120,9 @@ int lbfe_coexistence(double a, double b, double R, double T, double *rho_l, doub
  * when no GPU is usable.  The tile order of the streaming kernels (one
  * contiguous range of tiles per XCD, on from 2^26 nodes) can be forced with
  * the environment variable LBFE_XCD_REMAP=0/1, read here; it changes the
- * schedule only, never the result. */
+ * schedule only, never the result.  So does LBFE_CHAIN_CHUNK=1..64, which
+ * forces the number of z-planes each workgroup of the stencil chain marches
+ * through (otherwise chosen per grid). */
 int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out);
 
 /* Bytes of device workspace a context with these parameters needs. */

@@ -349,6 +349,11 @@ int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out) {
     // (+3 % at 256^3, +7 % at 512^3) and slower at 128^3 and in the FP32 and
     // FP16 forms, so it is chosen for FP64 from 2^24 nodes; LBFE_FUSED=0/1
     // forces either path.  Both give bitwise identical states.
+    // Planes per workgroup of the stencil chain (the result does not depend
+    // on it): chosen per grid; LBFE_CHAIN_CHUNK=1..64 forces it.
+    const char *cc = std::getenv("LBFE_CHAIN_CHUNK");
+    const int ccv = (cc && cc[0]) ? std::atoi(cc) : 0;
+    k.chain_cz = (ccv >= 1 && ccv <= 64) ? ccv : 0;
     const char *fu = std::getenv("LBFE_FUSED");
     const bool want = (fu && fu[0]) ? fu[0] == '1' : (q.precision == LBFE_FP64 && k.N >= (1u << 24));
     c->fused = want && !k.moving && !k.masked;  // the fused kernel has resting walls and no mask

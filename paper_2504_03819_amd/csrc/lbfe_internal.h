@@ -30,6 +30,7 @@ struct KP {
     double wall_u[4];          // (ux, uy) of the bottom and top walls
     int moving;                // some wall velocity is nonzero
     int masked;                // solid voxel mask (Bufs::nbr) instead of planes
+    int chain_cz;              // planes per stencil-chain workgroup; 0 = chosen per grid
 };
 
 // Device pointers of one context (all inside the caller's workspace).
