@@ -371,7 +371,8 @@ __global__ __launch_bounds__(CB) void k_chain(KP kp, const double *__restrict__ 
 // Planes per workgroup.  One workgroup fits a CU (LDS), and every march
 // starts with six pipeline-fill planes, so chunks of c planes cost the
 // busiest CU ceil(workgroups / CUs) x (c + 6) plane iterations; the chunk
-// length from 32 down to 1 that minimises it is taken (the longer on ties).
+// length from 64 down to 1 that minimises it is taken (the longer on ties).
+// (128-plane chunks, which the count favours at 512^3, measured slower.)
 constexpr unsigned kCUs = 256;  // MI355X
 static int chain_chunk(const KP &kp, unsigned tiles) {
     const int nzf = kp.z1 - kp.z0;
@@ -379,8 +380,8 @@ static int chain_chunk(const KP &kp, unsigned tiles) {
         const size_t wg = (size_t)tiles * ((nzf + c - 1) / c);
         return ((wg + kCUs - 1) / kCUs) * (size_t)(c + 6);
     };
-    int cz = 32;
-    for (int c = 16; c >= 1; c /= 2)
+    int cz = 64;
+    for (int c = 32; c >= 1; c /= 2)
         if (iters(c) < iters(cz)) cz = c;
     return cz;
 }

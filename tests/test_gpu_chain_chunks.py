@@ -1,6 +1,6 @@
 """The stencil chain marches each workgroup through a chunk of z-planes, the
 chunk length being chosen per grid.  Every node's arithmetic is the same
-whatever the chunk, so forcing other lengths (1, 3, 8, 32 planes, ragged
+whatever the chunk, so forcing other lengths (1, 3, 8, 32, 64 planes, ragged
 last chunks included) must leave the states and fields unchanged bit for
 bit, with walls (whose chemical potential a chunk takes from its first or
 last fluid plane) and on the fused path."""
@@ -52,7 +52,7 @@ def test_chain_chunk_length_changes_nothing(label, shape, walls, extra, env):
     T = eos.temperature(0.7 if walls else 0.85)
     nz, ny, nx = shape
     kw = dict(nx=nx, ny=ny, nz=nz, T=T, walls_z=int(walls), **extra)
-    sims = [_sim(c, env, **kw) for c in (None, 1, 3, 8, 32)]
+    sims = [_sim(c, env, **kw) for c in (None, 1, 3, 8, 32, 64)]
     rho0 = droplet_rho(shape, T, walls=walls, radius=min(ny, nx) / 3.0)
     g = np.random.Generator(np.random.PCG64(9))
     u0 = torch.tensor(0.02 * g.uniform(-1, 1, (3,) + shape))
