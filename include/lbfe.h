@@ -118,7 +118,8 @@ int lbfe_coexistence(double a, double b, double R, double T, double *rho_l, doub
  * NULL = default stream).  Allocates no device memory.
  * E_INVAL on a bad parameter (checked before any device call), E_DEVICE
  * when no GPU is usable.  The tile order of the streaming kernels (one
- * contiguous range of tiles per XCD, on from 2^26 nodes) can be forced with
+ * contiguous range of tiles per XCD; on from 2^26 nodes and, without a solid
+ * mask, whenever nx or ny is not a power of two) can be forced with
  * the environment variable LBFE_XCD_REMAP=0/1, read here; it changes the
  * schedule only, never the result.  So does LBFE_CHAIN_CHUNK=1..64, which
  * forces the number of z-planes each workgroup of the stencil chain marches

@@ -334,13 +334,19 @@ int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out) {
     k.lo = 0.05 * q.rho_l + 0.95 * q.rho_v;
     k.hi = 0.95 * q.rho_l + 0.05 * q.rho_v;
     // Tile-to-XCD remapping of the streaming kernels (each XCD takes one
-    // contiguous range of tiles instead of every eighth): on large grids the
+    // contiguous range of tiles instead of every eighth).  On large grids the
     // push-stream writes of the round-robin order span the whole active
     // z-window on every XCD, and the remapped order is 18-27 % faster at
-    // 512^3; up to 256^3 it is neutral.  On from 2^26 nodes;
+    // 512^3.  Measured on smaller grids it is also faster whenever nx or ny
+    // is not a power of two (160^3, 200^3, 192x192x96: +8-10 % in FP64 and
+    // FP32; 320^3 and 384x384x128 in FP32: +16-20 %), neutral at 128^3 and
+    // 256^3, and slower on the solid-mask path (its stencil gathers read
+    // neighbour rows that the round-robin order keeps in every XCD's L2).
     // LBFE_XCD_REMAP=0/1 forces it.
     const char *remap = std::getenv("LBFE_XCD_REMAP");
-    k.xcd_remap = (remap && remap[0]) ? (remap[0] == '1') : (k.N >= (1u << 26));
+    auto pow2 = [](unsigned v) { return (v & (v - 1)) == 0; };
+    const bool irregular = !pow2((unsigned)k.nx) || !pow2((unsigned)k.ny);
+    k.xcd_remap = (remap && remap[0]) ? (remap[0] == '1') : (k.N >= (1u << 26) || (irregular && !k.masked));
     // Step path: separate moments and collide-stream passes, or the fused
     // collide-stream-moments kernel, which saves the moments pass's
     // population read but re-reads a one-node ring of populations per tile
