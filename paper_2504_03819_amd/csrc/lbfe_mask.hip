@@ -21,6 +21,7 @@
 // phi, Q; a solid node with no fluid neighbour gets rho = mu = 0 and is read
 // by no fluid stencil.
 #include "lbfe_device.h"
+#include "lbfe_zring.h"
 
 namespace lbfe {
 namespace {
@@ -278,12 +279,118 @@ __global__ __launch_bounds__(kBlock) void k_check_rho_m(KP kp, const unsigned *n
     if (!(r > 0.0 && kp.b * r < 1.0)) *flag = 1;
 }
 
+// The same Q for FP64 phi, whose per-node gathers (54 eight-byte loads per
+// node) miss L1 more than the FP32 ones: the three components of four
+// consecutive planes of a 32 x 16 tile (plus a one-node halo) are staged in
+// an LDS ring and each point reads its stencil there.
+__global__ __launch_bounds__(ZCB) void k_q_z(KP kp, const unsigned *nbr, const double *phi, double *Q, int cz) {
+    __shared__ double lds[4][3][ZNR];
+    int x0, y0, zs, ze;
+    ztile(kp, cz, 0, kp.nz, x0, y0, zs, ze);
+    const size_t N = kp.N;
+    ZRing<3> R;
+    R.init(kp, lds, x0, y0);
+    for (int c = 0; c < 3; ++c) R.src[c] = phi + c * N;
+    R.march(zs, ze, [&](int k) {
+        if (!R.own) return;
+        double sx = 0.0, sy = 0.0, sz = 0.0;
+#pragma unroll
+        for (int a = -1; a <= 1; ++a)
+#pragma unroll
+            for (int c = -1; c <= 1; ++c) {
+                const double w = w1(a) * w1(c) / 6.0;
+                sx += w * (R.at(0, k + c, 1, a) - R.at(0, k + c, -1, a));
+                sy += w * (R.at(1, k + c, a, 1) - R.at(1, k + c, a, -1));
+                sz += w * (R.at(2, k + 1, a, c) - R.at(2, k - 1, a, c));
+            }
+        const size_t n = (size_t)k * kp.plane + R.node;
+        const bool solid = solid_at(nbr[n]);
+        Q[n] = solid ? 0.0 : -9.0 * sx;
+        Q[N + n] = solid ? 0.0 : -9.0 * sy;
+        Q[2 * N + n] = solid ? 0.0 : -9.0 * sz;
+    });
+}
+
+// k_mu_m and k_fphi_m with their stencil field (rho, mu) staged in an LDS
+// ring instead of gathered through L1: the same sums in the same order.
+__global__ __launch_bounds__(ZCB) void k_mu_z(KP kp, const unsigned *nbr, const double *rho, double *mu, int cz) {
+    __shared__ double lds[4][1][ZNR];
+    int x0, y0, zs, ze;
+    ztile(kp, cz, 0, kp.nz, x0, y0, zs, ze);
+    ZRing<1> R;
+    R.init(kp, lds, x0, y0);
+    R.src[0] = rho;
+    R.march(zs, ze, [&](int k) {
+        if (!R.own) return;
+        const size_t n = (size_t)k * kp.plane + R.node;
+        if (solid_at(nbr[n])) return;
+        const double r0 = R.at(0, k, 0, 0);
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            if (i == kRest) continue;
+            s += wi(i) * (R.at(0, k + czi(i), cxi(i), cyi(i)) - r0);
+        }
+        mu[n] = mu_bulk(kp, r0) - kp.kappa * 6.0 * s;
+    });
+}
+
+template <int P>
+__global__ __launch_bounds__(ZCB) void k_fphi_z(KP kp, const unsigned *nbr, const double *rho, const void *jq,
+                                                const double *mu, void *Fq, void *phiq, int cz) {
+    using real = real_t<P>;
+    __shared__ double lds[4][1][ZNR];
+    int x0, y0, zs, ze;
+    ztile(kp, cz, 0, kp.nz, x0, y0, zs, ze);
+    const size_t N = kp.N;
+    real *F = (real *)Fq, *phi = (real *)phiq;
+    const real *j = (const real *)jq;
+    ZRing<1> R;
+    R.init(kp, lds, x0, y0);
+    R.src[0] = mu;
+    R.march(zs, ze, [&](int k) {
+        if (!R.own) return;
+        const size_t n = (size_t)k * kp.plane + R.node;
+        if (solid_at(nbr[n])) {
+            for (int a = 0; a < 3; ++a) F[a * N + n] = phi[a * N + n] = (real)0;
+            return;
+        }
+        double gx = 0.0, gy = 0.0, gz = 0.0;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            if (i == kRest) continue;
+            const double v = 3.0 * wi(i) * R.at(0, k + czi(i), cxi(i), cyi(i));
+            if (cxi(i)) gx += cxi(i) * v;
+            if (cyi(i)) gy += cyi(i) * v;
+            if (czi(i)) gz += czi(i) * v;
+        }
+        const double rd = rho[n];
+        const double c1 = 1.0 / 3.0 - rd;
+        const real Fx = (real)(c1 * gx), Fy = (real)(c1 * gy), Fz = (real)(c1 * gz);
+        const real ir = (real)1 / (real)rd;
+        const real ux = (j[n] + (real)0.5 * Fx) * ir;
+        const real uy = (j[N + n] + (real)0.5 * Fy) * ir;
+        const real uz = (j[2 * N + n] + (real)0.5 * Fz) * ir;
+        const real c2 = (real)((1.0 + R.at(0, k, 0, 0) - rd) * (1.0 / 3.0));  // p_m - rho/3
+        F[n] = Fx;
+        F[N + n] = Fy;
+        F[2 * N + n] = Fz;
+        phi[n] = c2 * ux;
+        phi[N + n] = c2 * uy;
+        phi[2 * N + n] = c2 * uz;
+    });
+}
+
 template <int P> void chain_m(hipStream_t s, const KP &kp, const Bufs &b) {
     const unsigned g = nblocks(kp.N);
-    k_mu_m<<<g, kBlock, 0, s>>>(kp, b.nbr, b.rho, b.mu);
+    const dim3 gz = zgrid(kp, 0, kp.nz);
+    k_mu_z<<<gz, ZCB, 0, s>>>(kp, b.nbr, b.rho, b.mu, kZChunk);
     k_wall_mu_m<<<g, kBlock, 0, s>>>(kp, b.nbr, b.mu);
-    k_fphi_m<P><<<g, kBlock, 0, s>>>(kp, b.nbr, b.rho, b.j, b.mu, b.F, b.phi);
-    k_q_m<P><<<g, kBlock, 0, s>>>(kp, b.nbr, b.phi, b.Q);
+    k_fphi_z<P><<<gz, ZCB, 0, s>>>(kp, b.nbr, b.rho, b.j, b.mu, b.F, b.phi, kZChunk);
+    if constexpr (P == LBFE_FP64)
+        k_q_z<<<zgrid(kp, 0, kp.nz), ZCB, 0, s>>>(kp, b.nbr, (const double *)b.phi, (double *)b.Q, kZChunk);
+    else
+        k_q_m<P><<<g, kBlock, 0, s>>>(kp, b.nbr, b.phi, b.Q);
 }
 
 template <class Fn> hipError_t dispatch(int prec, Fn &&fn) {
