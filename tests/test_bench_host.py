@@ -1,0 +1,59 @@
+"""Host-side pieces of bench.py that feed the roofline fields: the
+algorithmic bytes per node of each storage form and the calibration of the
+rocprofv3 HBM counters against a copy of known size."""
+import csv
+import json
+
+import pytest
+
+import bench
+
+
+def test_algorithmic_bytes_per_node():
+    # 27 populations read and written once per node and step
+    assert bench.alg_bytes_per_node("fp64") == 432
+    assert bench.alg_bytes_per_node("fp32") == 216
+    assert bench.alg_bytes_per_node("fp16dev") == 108
+    # 26 FP16 deviations and the rest population in FP32
+    assert bench.alg_bytes_per_node("fp16dev_f0fp32") == 2 * (26 * 2 + 4)
+
+
+def _counter_csv(path, counter, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for kernel, value in rows:
+            w.writerow({"Kernel_Name": kernel, "Counter_Name": counter, "Counter_Value": value})
+        # a row of another counter must be ignored
+        w.writerow({"Kernel_Name": "k_collide<0>", "Counter_Name": "SQ_WAVES", "Counter_Value": 1e9})
+
+
+def test_counter_calibration(tmp_path):
+    gib_kib = (1 << 30) / 1024.0
+    copy = "__amd_rocclr_copyBuffer"
+    # the counters read half the copy's bytes on fetch and all on write; a
+    # smaller copy dispatch of the same run must not set the factor
+    _counter_csv(tmp_path / "f.csv", "FETCH_SIZE",
+                 [(copy, gib_kib / 2), (copy, 10.0), ("k_collide<0>", 1000.0), ("k_collide<0>", 1200.0),
+                  ("k_moments<0>", 300.0)])
+    _counter_csv(tmp_path / "w.csv", "WRITE_SIZE",
+                 [(copy, gib_kib), (copy, 10.0), ("k_collide<0>", 500.0), ("k_collide<0>", 500.0),
+                  ("k_moments<0>", 40.0)])
+    out = tmp_path / "c.json"
+    bench.summarize_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), "fp64", "moving", str(out))
+    c = json.load(open(out))
+    assert c["copy_fetch_factor"] == pytest.approx(2.0)
+    assert c["copy_write_factor"] == pytest.approx(1.0)
+    assert c["fetch_kib_per_launch"] == pytest.approx(1100.0)
+    assert c["bytes_per_launch"] == pytest.approx((1100.0 * 2.0 + 500.0) * 1024.0)
+    assert c["kernels"]["fetch_kib"]["k_moments<0>"] == pytest.approx(300.0)
+    assert c["source_hash"] == bench.kernel_source_hash()
+    assert (c["form"], c["workload"]) == ("fp64", "moving")
+
+
+def test_counter_calibration_needs_the_copy(tmp_path):
+    _counter_csv(tmp_path / "f.csv", "FETCH_SIZE", [("k_collide<0>", 1000.0)])
+    _counter_csv(tmp_path / "w.csv", "WRITE_SIZE", [("k_collide<0>", 500.0)])
+    with pytest.raises(SystemExit):
+        bench.summarize_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), "fp64", "moving",
+                                 str(tmp_path / "c.json"))
