@@ -167,8 +167,9 @@ int lbfe_init_density(lbfe_ctx *ctx, const double *rho0_dev, const double *u0_de
  * bounce-back.  Checks the divergence flag every check_every steps and at
  * the end (a synchronisation): E_DIVERGED, with the step in lbfe_last_error.
  * Each step is a moments pass, the stencil chain and a collide-stream
- * pass, or, for FP64 contexts of at least 2^24 nodes without moving walls
- * or a mask, the stencil chain and a collide-stream kernel that also forms
+ * pass, or, for FP64 contexts of at least 2^24 nodes with power-of-two nx
+ * and ny and without moving walls or a mask, the stencil chain and a
+ * collide-stream kernel that also forms
  * the next step's density and momentum (no moments pass); both give
  * bitwise identical states.  The environment variable LBFE_FUSED=0/1 at
  * lbfe_create forces the first or the second path. */

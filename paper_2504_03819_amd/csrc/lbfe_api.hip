@@ -347,21 +347,27 @@ int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out) {
     auto pow2 = [](unsigned v) { return (v & (v - 1)) == 0; };
     const bool irregular = !pow2((unsigned)k.nx) || !pow2((unsigned)k.ny);
     k.xcd_remap = (remap && remap[0]) ? (remap[0] == '1') : (k.N >= (1u << 26) || (irregular && !k.masked));
-    // Step path: separate moments and collide-stream passes, or the fused
-    // collide-stream-moments kernel, which saves the moments pass's
-    // population read but re-reads a one-node ring of populations per tile
-    // and runs twice the vector instructions per node at two waves per SIMD.
-    // Measured on gfx950 the fused step is faster only in FP64 on large grids
-    // (+3 % at 256^3, +7 % at 512^3) and slower at 128^3 and in the FP32 and
-    // FP16 forms, so it is chosen for FP64 from 2^24 nodes; LBFE_FUSED=0/1
-    // forces either path.  Both give bitwise identical states.
     // Planes per workgroup of the stencil chain (the result does not depend
     // on it): chosen per grid; LBFE_CHAIN_CHUNK=1..64 forces it.
     const char *cc = std::getenv("LBFE_CHAIN_CHUNK");
     const int ccv = (cc && cc[0]) ? std::atoi(cc) : 0;
     k.chain_cz = (ccv >= 1 && ccv <= 64) ? ccv : 0;
+    // Step path: separate moments and collide-stream passes, or the fused
+    // collide-stream-moments kernel, which saves the moments pass's
+    // population read but re-reads a one-node ring of populations per tile
+    // and runs twice the vector instructions per node at two waves per SIMD.
+    // Measured on gfx950 the fused step is faster only in FP64 on large grids
+    // with power-of-two nx and ny (+3 % at 256^3, +7 % at 512^3); it is
+    // slower at 128^3, in the FP32 and FP16 forms, and on most large grids
+    // whose nx or ny is not a power of two, where the two-read path gains
+    // from the XCD-contiguous tile order (288^3, 320^3, 352x352x256,
+    // 480x480x160, 200x200x512: 5-16 % slower; 448x448x128 even; 384x384x128
+    // 5 % faster).  So it is chosen for FP64 from 2^24 nodes with
+    // power-of-two nx and ny; LBFE_FUSED=0/1 forces either path.  Both give
+    // bitwise identical states.
     const char *fu = std::getenv("LBFE_FUSED");
-    const bool want = (fu && fu[0]) ? fu[0] == '1' : (q.precision == LBFE_FP64 && k.N >= (1u << 24));
+    const bool want = (fu && fu[0]) ? fu[0] == '1'
+                                    : (q.precision == LBFE_FP64 && k.N >= (1u << 24) && !irregular);
     c->fused = want && !k.moving && !k.masked;  // the fused kernel has resting walls and no mask
     *out = c;
     return LBFE_OK;
