@@ -6,15 +6,19 @@
 //
 // Every node carries one 32-bit neighbour word: bit i (i = 0..26) is set
 // when x + c_i is solid, so bit 13 tells whether the node itself is solid.
-// It is built once per mask; all kernels below are per-node gathers over the
-// whole grid that read it:
+// It is built once per mask; all kernels below work per node over the whole
+// grid and read it (the _m kernels gather their neighbours through L1/L2,
+// the _z stencils stage their input field in the z-marching LDS ring of
+// lbfe_zring.h):
 //   k_moments_m     rho, j of the fluid nodes (order of moments())
 //   k_wall_rho_m    rho at solid nodes with a fluid neighbour, Eqs. (37)-(38)
-//   k_mu_m          mu = mu0(rho) - kappa lap_h rho at fluid nodes, Eq. (32)
+//   k_mu_z          mu = mu0(rho) - kappa lap_h rho at fluid nodes, Eq. (32)
+//                   (k_mu_m for the initialiser)
 //   k_wall_mu_m     mu at solid nodes, Eq. (36)
-//   k_fphi_m        G = grad_h mu, F = (1/3 - rho) G, u = (j + F/2)/rho,
+//   k_fphi_z        G = grad_h mu, F = (1/3 - rho) G, u = (j + F/2)/rho,
 //                   phi = (p_m - rho/3) u at fluid nodes, Eqs. (11)-(12), (27)
-//   k_q_m           Q_aa = -3 d_a phi_a at fluid nodes, Eq. (27)
+//   k_q_z / k_q_m   Q_aa = -3 d_a phi_a at fluid nodes, Eq. (27) (FP64 /
+//                   FP32 phi)
 //   k_collide_m     collision and push-streaming; a link that ends on a
 //                   solid node returns into slot opp(i) of its own node
 // Solid nodes hold no populations (their slots stay zero) and zero j, F,
@@ -129,49 +133,6 @@ __global__ __launch_bounds__(kBlock) void k_wall_mu_m(KP kp, const unsigned *nbr
     const unsigned w = nbr[n];
     if (!solid_at(w)) return;
     mu[n] = fluid_average(kp, w, mu, n);
-}
-
-template <int P>
-__global__ __launch_bounds__(kBlock) void k_fphi_m(KP kp, const unsigned *nbr, const double *rho, const void *jq,
-                                                   const double *mu, void *Fq, void *phiq) {
-    using real = real_t<P>;
-    const unsigned n = tile_id(kp) * kBlock + threadIdx.x;
-    if (n >= kp.N) return;
-    const size_t N = kp.N;
-    real *F = (real *)Fq, *phi = (real *)phiq;
-    const bool solid = solid_at(nbr[n]);
-    int x, y, z;
-    decompose(kp, n, x, y, z);
-    const Nb nb(kp, x, y, z);
-    // grad_h mu = 3 sum_i w_i c_i mu(x + c_i)
-    double gx = 0.0, gy = 0.0, gz = 0.0;
-#pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        if (i == kRest) continue;
-        const double v = 3.0 * wi(i) * mu[nb.at(cxi(i), cyi(i), czi(i))];
-        if (cxi(i)) gx += cxi(i) * v;
-        if (cyi(i)) gy += cyi(i) * v;
-        if (czi(i)) gz += czi(i) * v;
-    }
-    if (solid) {
-        for (int a = 0; a < 3; ++a) F[a * N + n] = phi[a * N + n] = (real)0;
-        return;
-    }
-    const double rd = rho[n];
-    const double c1 = 1.0 / 3.0 - rd;
-    const real Fx = (real)(c1 * gx), Fy = (real)(c1 * gy), Fz = (real)(c1 * gz);
-    const real *j = (const real *)jq;
-    const real ir = (real)1 / (real)rd;
-    const real ux = (j[n] + (real)0.5 * Fx) * ir;
-    const real uy = (j[N + n] + (real)0.5 * Fy) * ir;
-    const real uz = (j[2 * N + n] + (real)0.5 * Fz) * ir;
-    const real c2 = (real)((1.0 + mu[n] - rd) * (1.0 / 3.0));  // p_m - rho/3
-    F[n] = Fx;
-    F[N + n] = Fy;
-    F[2 * N + n] = Fz;
-    phi[n] = c2 * ux;
-    phi[N + n] = c2 * uy;
-    phi[2 * N + n] = c2 * uz;
 }
 
 // Q_aa = -3 d_a,h phi_a = -9 sum_i w_i c_ia phi_a(x + c_i)
@@ -311,8 +272,10 @@ __global__ __launch_bounds__(ZCB) void k_q_z(KP kp, const unsigned *nbr, const d
     });
 }
 
-// k_mu_m and k_fphi_m with their stencil field (rho, mu) staged in an LDS
-// ring instead of gathered through L1: the same sums in the same order.
+// The step's mu (the sums of k_mu_m, in the same order) and its force,
+// velocity and phi, with the stencil field (rho, mu) staged in an LDS ring:
+// grad_h mu = 3 sum_i w_i c_i mu(x + c_i), F = (1/3 - rho) grad_h mu,
+// u = (j + F/2)/rho, phi = (p_m - rho/3) u; F = phi = 0 at solid nodes.
 __global__ __launch_bounds__(ZCB) void k_mu_z(KP kp, const unsigned *nbr, const double *rho, double *mu, int cz) {
     __shared__ double lds[4][1][ZNR];
     int x0, y0, zs, ze;
