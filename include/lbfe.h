@@ -97,14 +97,39 @@ typedef struct lbfe_params {
     int32_t solid_mask;  /* 1: the solid nodes come from a voxel mask given
                             by lbfe_set_solid (needs walls_z = 0, adjoint =
                             0, resting walls); 0: none or the wall planes */
+    /* Schedule.  None of these changes a result bit; 0 lets lbfe_create
+     * choose per grid, and lbfe_get_params reports the choice made. */
+    int32_t step_path;   /* LBFE_PATH_*: how one step is split into kernels */
+    int32_t tile_order;  /* LBFE_ORDER_*: how tiles are dealt to the XCDs   */
+    int32_t chain_chunk; /* z-planes per workgroup of the stencil chain,
+                            1..64                                          */
 } lbfe_params;
+
+/* ---- schedule choices (lbfe_params.step_path, .tile_order) ------------- */
+/* LBFE_PATH_TWO_PASS  a moments pass over the stored populations, the
+ *                     stencil chain, then collide + stream: the populations
+ *                     are read twice per step.
+ * LBFE_PATH_FUSED     the stencil chain, then one kernel that collides,
+ *                     streams and forms the next step's density and momentum
+ *                     (Eq. (11)): the populations are read once per step.
+ *                     Not with moving walls or a solid mask, and only when
+ *                     one z-plane of the lattice is below 2 GiB.
+ * LBFE_ORDER_ROUND_ROBIN  workgroups in launch order (the hardware deals them
+ *                     to the 8 XCDs in turn).
+ * LBFE_ORDER_XCD      each XCD takes one contiguous range of tiles, so
+ *                     neighbouring tiles share that XCD's L2. */
+#define LBFE_AUTO 0
+#define LBFE_PATH_TWO_PASS 1
+#define LBFE_PATH_FUSED 2
+#define LBFE_ORDER_ROUND_ROBIN 1
+#define LBFE_ORDER_XCD 2
 
 typedef struct lbfe_ctx lbfe_ctx;
 
 /* Fill *p with the paper's defaults (Sec. III): a = 9/392, b = 2/21, R = 1,
  * T = 0.7 T_c, kappa = 0.02, nu = 0.15, all omega_k = 1, corr4 on,
  * periodic 32^3, neutral wetting, resting walls, FP64, check_every = 100,
- * adjoint off. */
+ * adjoint off, schedule LBFE_AUTO. */
 int lbfe_params_default(lbfe_params *p);
 
 /* Coexistence pair of the vdW EOS at temperature T from equal chemical
@@ -117,13 +142,12 @@ int lbfe_coexistence(double a, double b, double R, double T, double *rho_l, doub
  * to the current HIP device and the given stream (hipStream_t as void*;
  * NULL = default stream).  Allocates no device memory.
  * E_INVAL on a bad parameter (checked before any device call), E_DEVICE
- * when no GPU is usable.  The tile order of the streaming kernels (one
- * contiguous range of tiles per XCD; on from 2^26 nodes and, without a solid
- * mask, whenever nx or ny is not a power of two) can be forced with
- * the environment variable LBFE_XCD_REMAP=0/1, read here; it changes the
- * schedule only, never the result.  So does LBFE_CHAIN_CHUNK=1..64, which
- * forces the number of z-planes each workgroup of the stencil chain marches
- * through (otherwise chosen per grid). */
+ * when no GPU is usable.  Schedule fields left at LBFE_AUTO are chosen per
+ * grid: the fused step path for FP64 contexts of at least 2^24 nodes where
+ * it is allowed, else the two-pass path; the XCD tile order from
+ * 2^26 nodes and, without a solid mask, whenever nx or ny is not a power of
+ * two; the chain chunk that minimises the busiest CU's plane iterations.
+ * Asking for the fused path where it is not allowed is E_INVAL. */
 int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out);
 
 /* Bytes of device workspace a context with these parameters needs. */
@@ -134,7 +158,8 @@ int lbfe_workspace_bytes(const lbfe_params *p, size_t *bytes);
  * the context; the library never frees it.  E_NOMEM if too small. */
 int lbfe_bind_workspace(lbfe_ctx *ctx, void *workspace_dev, size_t bytes);
 
-/* Copy the context's parameters, with derived rho_l/rho_v, into *out. */
+/* Copy the context's parameters, with derived rho_l/rho_v and the schedule
+ * actually chosen (no LBFE_AUTO left), into *out. */
 int lbfe_get_params(const lbfe_ctx *ctx, lbfe_params *out);
 
 /* Solid voxel mask (params.solid_mask = 1): the halfway bounce-back of
@@ -166,13 +191,11 @@ int lbfe_init_density(lbfe_ctx *ctx, const double *rho0_dev, const double *u0_de
  * Eqs. (21)-(26), inverse transform and streaming Eq. (10) with halfway
  * bounce-back.  Checks the divergence flag every check_every steps and at
  * the end (a synchronisation): E_DIVERGED, with the step in lbfe_last_error.
- * Each step is a moments pass, the stencil chain and a collide-stream
- * pass, or, for FP64 contexts of at least 2^24 nodes with power-of-two nx
- * and ny and without moving walls or a mask, the stencil chain and a
- * collide-stream kernel that also forms
- * the next step's density and momentum (no moments pass); both give
- * bitwise identical states.  The environment variable LBFE_FUSED=0/1 at
- * lbfe_create forces the first or the second path. */
+ * Each step runs as params.step_path says: a moments pass, the stencil
+ * chain and a collide-stream pass (LBFE_PATH_TWO_PASS), or the stencil
+ * chain and a collide-stream kernel that also forms the next step's density
+ * and momentum (LBFE_PATH_FUSED, no moments pass); both give bitwise
+ * identical states. */
 int lbfe_step(lbfe_ctx *ctx, int64_t nsteps);
 
 /* Timing variant of lbfe_step for benchmarks: the same launches, with HIP

@@ -25,7 +25,7 @@ struct lbfe_ctx {
     int lcur = 0;  // index of the current adjoint lattice
     int64_t step = 0;
     bool bound = false, initialised = false, adj_seeded = false;
-    bool fused = false;   // fused collide-stream-moments step (LBFE_FUSED=1)
+    bool fused = false;   // fused collide-stream-moments step (LBFE_PATH_FUSED)
     bool aux_ok = false;  // rho, j, mu0 hold the moments of f[cur]
     bool mask_set = false;  // a solid mask has been given (solid_mask = 1)
     bool lam_pending = false;  // lam[lcur] lacks its last term (see the adjoint kernels)
@@ -121,6 +121,9 @@ std::string validate(const lbfe_params &p) {
     if (p.solid_mask != 0 && p.solid_mask != 1) return "solid_mask must be 0 or 1";
     if (p.solid_mask && p.walls_z) return "solid_mask replaces walls_z (put the planes into the mask)";
     if (p.solid_mask && p.adjoint) return "the adjoint does not cover solid masks";
+    if (p.step_path < LBFE_AUTO || p.step_path > LBFE_PATH_FUSED) return "unknown step_path";
+    if (p.tile_order < LBFE_AUTO || p.tile_order > LBFE_ORDER_XCD) return "unknown tile_order";
+    if (p.chain_chunk < 0 || p.chain_chunk > 64) return "chain_chunk must be 0 (chosen per grid) or 1..64";
     return "";
 }
 
@@ -128,6 +131,15 @@ std::string validate(const lbfe_params &p) {
 struct Layout {
     size_t f0, f1, rho, j, mu, mu0, F, Q, nbr, phi, flag, part, red, lam0, lam1, abuf, agrad, total;
 };
+
+bool moving_walls(const lbfe_params &p) {
+    return p.wall_u[0] != 0.0 || p.wall_u[1] != 0.0 || p.wall_u[2] != 0.0 || p.wall_u[3] != 0.0;
+}
+
+// the fused step path is possible: resting walls, no mask, 32-bit plane offsets
+bool fused_possible(const lbfe_params &p) {
+    return !moving_walls(p) && !p.solid_mask && fused_plane_ok(p.precision, (size_t)p.nx * p.ny);
+}
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -333,42 +345,43 @@ int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out) {
     k.wet_value = q.wet_value;
     k.lo = 0.05 * q.rho_l + 0.95 * q.rho_v;
     k.hi = 0.95 * q.rho_l + 0.05 * q.rho_v;
-    // Tile-to-XCD remapping of the streaming kernels (each XCD takes one
-    // contiguous range of tiles instead of every eighth).  On large grids the
-    // push-stream writes of the round-robin order span the whole active
-    // z-window on every XCD, and the remapped order is 18-27 % faster at
-    // 512^3.  Measured on smaller grids it is also faster whenever nx or ny
-    // is not a power of two (160^3, 200^3, 192x192x96: +8-10 % in FP64 and
-    // FP32; 320^3 and 384x384x128 in FP32: +16-20 %), neutral at 128^3 and
-    // 256^3, and slower on the solid-mask path (its stencil gathers read
-    // neighbour rows that the round-robin order keeps in every XCD's L2).
-    // LBFE_XCD_REMAP=0/1 forces it.
-    const char *remap = std::getenv("LBFE_XCD_REMAP");
+    // Schedule (none of it changes a result bit).  Tile order of the
+    // streaming kernels: with the hardware's round-robin dealing every XCD
+    // works on every eighth tile, and on large grids the push-stream writes
+    // then span the whole active z-window on every XCD; one contiguous range
+    // of tiles per XCD is 18-27 % faster at 512^3, and on smaller grids also
+    // faster whenever nx or ny is not a power of two (160^3, 200^3,
+    // 192x192x96: +8-10 %; 320^3 and 384x384x128 in FP32: +16-20 %), neutral
+    // at 128^3 and 256^3, and slower on the solid-mask path (its stencil
+    // gathers read neighbour rows that the round-robin order keeps in every
+    // XCD's L2).
     auto pow2 = [](unsigned v) { return (v & (v - 1)) == 0; };
     const bool irregular = !pow2((unsigned)k.nx) || !pow2((unsigned)k.ny);
-    k.xcd_remap = (remap && remap[0]) ? (remap[0] == '1') : (k.N >= (1u << 26) || (irregular && !k.masked));
-    // Planes per workgroup of the stencil chain (the result does not depend
-    // on it): chosen per grid; LBFE_CHAIN_CHUNK=1..64 forces it.
-    const char *cc = std::getenv("LBFE_CHAIN_CHUNK");
-    const int ccv = (cc && cc[0]) ? std::atoi(cc) : 0;
-    k.chain_cz = (ccv >= 1 && ccv <= 64) ? ccv : 0;
-    // Step path: separate moments and collide-stream passes, or the fused
-    // collide-stream-moments kernel, which saves the moments pass's
-    // population read but re-reads a one-node ring of populations per tile
-    // and runs twice the vector instructions per node at two waves per SIMD.
-    // Measured on gfx950 the fused step is faster only in FP64 on large grids
-    // with power-of-two nx and ny (+3 % at 256^3, +7 % at 512^3); it is
-    // slower at 128^3, in the FP32 and FP16 forms, and on most large grids
-    // whose nx or ny is not a power of two, where the two-read path gains
-    // from the XCD-contiguous tile order (288^3, 320^3, 352x352x256,
-    // 480x480x160, 200x200x512: 5-16 % slower; 448x448x128 even; 384x384x128
-    // 5 % faster).  So it is chosen for FP64 from 2^24 nodes with
-    // power-of-two nx and ny; LBFE_FUSED=0/1 forces either path.  Both give
-    // bitwise identical states.
-    const char *fu = std::getenv("LBFE_FUSED");
-    const bool want = (fu && fu[0]) ? fu[0] == '1'
-                                    : (q.precision == LBFE_FP64 && k.N >= (1u << 24) && !irregular);
-    c->fused = want && !k.moving && !k.masked;  // the fused kernel has resting walls and no mask
+    if (q.tile_order == LBFE_AUTO)
+        q.tile_order = (k.N >= (1u << 26) || (irregular && !k.masked)) ? LBFE_ORDER_XCD : LBFE_ORDER_ROUND_ROBIN;
+    k.xcd_remap = q.tile_order == LBFE_ORDER_XCD;
+    // Planes per workgroup of the stencil chain: chosen per grid unless given.
+    k.chain_cz = q.chain_chunk;
+    q.chain_chunk = k.chain_cz = chain_chunk_for(k);
+    // Step path: the fused collide-stream-moments kernel reads the
+    // populations once per step; it has resting walls, no solid mask, and
+    // addresses one z-plane of the lattice with 32-bit offsets.  Measured on
+    // gfx950 it is faster in FP64 on large grids (256^3: 2.44 against
+    // 2.76 ms per step; 512^3: 19.0 against 22.1 ms) and slower in the FP32
+    // and FP16 forms, whose collide-stream pass alone runs closer to the
+    // bandwidth than the fused kernel with its ring of recollided nodes
+    // (512^3 FP32: 12.6 against 11.6 ms per step).
+    const bool fused_ok = fused_possible(q);
+    if (q.step_path == LBFE_AUTO)
+        q.step_path = fused_ok && q.precision == LBFE_FP64 && k.N >= (1u << 24) ? LBFE_PATH_FUSED : LBFE_PATH_TWO_PASS;
+    if (q.step_path == LBFE_PATH_FUSED && !fused_ok) {
+        std::fprintf(stderr, "lbfe_create: the fused step path needs resting walls, no solid mask and "
+                             "a lattice z-plane below 2 GiB\n");
+        delete c;
+        return LBFE_E_INVAL;
+    }
+    c->fused = q.step_path == LBFE_PATH_FUSED;
+    c->p = q;
     *out = c;
     return LBFE_OK;
 }

@@ -386,9 +386,14 @@ static int chain_chunk(const KP &kp, unsigned tiles) {
     return cz;
 }
 
+int chain_chunk_for(const KP &kp) {
+    const unsigned ntx = (kp.nx + TX - 1) / TX, nty = (kp.ny + TY - 1) / TY;
+    return kp.chain_cz > 0 ? kp.chain_cz : chain_chunk(kp, ntx * nty);
+}
+
 hipError_t launch_chain(hipStream_t s, int prec, const KP &kp, const Bufs &b) {
     const unsigned ntx = (kp.nx + TX - 1) / TX, nty = (kp.ny + TY - 1) / TY;
-    const int cz = kp.chain_cz > 0 ? kp.chain_cz : chain_chunk(kp, ntx * nty);
+    const int cz = chain_chunk_for(kp);
     const int nzf = kp.z1 - kp.z0;
     const dim3 grid(ntx * nty, (nzf + cz - 1) / cz);
     switch (prec) {

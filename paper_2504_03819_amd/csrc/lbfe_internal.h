@@ -30,7 +30,7 @@ struct KP {
     double wall_u[4];          // (ux, uy) of the bottom and top walls
     int moving;                // some wall velocity is nonzero
     int masked;                // solid voxel mask (Bufs::nbr) instead of planes
-    int chain_cz;              // planes per stencil-chain workgroup; 0 = chosen per grid
+    int chain_cz;              // planes per stencil-chain workgroup
 };
 
 // Device pointers of one context (all inside the caller's workspace).
@@ -63,10 +63,14 @@ hipError_t launch_aux(hipStream_t s, int prec, const KP &kp, const Bufs &b, int 
 // unfused moments, chain, collide-stream.  ev5: optional timing events.
 hipError_t launch_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, bool fused, bool refresh,
                        hipEvent_t *ev5);
-// collide + push-stream + rho, j, mu0 of the streamed state (lbfe_fused.hip)
+// collide + stream + rho, j, mu0 of the streamed state (lbfe_fused.hip);
+// fused_plane_ok: one z-plane of the lattice fits its 32-bit plane offsets
 hipError_t launch_fused(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur);
-// mu, F and Q of the current rho, j (lbfe_chain.hip)
+bool fused_plane_ok(int prec, size_t plane);
+// mu, F and Q of the current rho, j (lbfe_chain.hip); chain_chunk_for: the
+// planes per workgroup, kp.chain_cz if set, else chosen for the grid
 hipError_t launch_chain(hipStream_t s, int prec, const KP &kp, const Bufs &b);
+int chain_chunk_for(const KP &kp);
 hipError_t launch_export(hipStream_t s, int prec, const KP &kp, const Bufs &b, int which, double *out);
 hipError_t launch_reduce(hipStream_t s, int prec, const KP &kp, const Bufs &b);
 hipError_t launch_get_pop(hipStream_t s, int prec, const KP &kp, const Bufs &b, const void *f, double *out);

@@ -4,8 +4,6 @@ whatever the chunk, so forcing other lengths (1, 3, 8, 32, 64 planes, ragged
 last chunks included) must leave the states and fields unchanged bit for
 bit, with walls (whose chemical potential a chunk takes from its first or
 last fluid plane) and on the fused path."""
-import os
-
 import numpy as np
 import pytest
 import torch
@@ -17,42 +15,33 @@ pytestmark = pytest.mark.gpu
 
 OM = [1.0, 1.0, 1.0, 0.5] + [1.0] * 7
 CASES = [
-    # (label, shape (nz, ny, nx), walls, extra, env)
-    ("periodic fp64 ragged", (40, 37, 70), False, dict(precision="fp64"), {}),
-    ("walls phi fp32", (34, 21, 45), True, dict(precision="fp32", wet_mode=1, wet_value=1.4, omega=OM), {}),
-    ("walls drho fp64 3-plane", (3, 20, 33), True, dict(precision="fp64", wet_mode=2, wet_value=0.9, omega=OM), {}),
+    # (label, shape (nz, ny, nx), walls, extra, schedule)
+    ("periodic fp64 ragged", (40, 37, 70), False, dict(precision="fp64"), {"step_path": 1}),
+    ("walls phi fp32", (34, 21, 45), True, dict(precision="fp32", wet_mode=1, wet_value=1.4, omega=OM),
+     {"step_path": 1}),
+    ("walls drho fp64 3-plane", (3, 20, 33), True, dict(precision="fp64", wet_mode=2, wet_value=0.9, omega=OM),
+     {"step_path": 1}),
+    ("fused periodic fp32 ragged", (40, 37, 70), False, dict(precision="fp32"), {"step_path": 2}),
     ("fused walls fp64", (21, 26, 40), True, dict(precision="fp64", wet_mode=1, wet_value=1.3, omega=OM),
-     {"LBFE_FUSED": "1"}),
+     {"step_path": 2}),
 ]
 
 
-def _sim(chunk, env, **kw):
-    env = dict(env)
-    if chunk:
-        env["LBFE_CHAIN_CHUNK"] = str(chunk)
-    old = {k: os.environ.get(k) for k in env}
-    os.environ.update(env)
-    try:
-        return make_sim(**kw)
-    finally:
-        for k, v in old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
+def _sim(chunk, sched, **kw):
+    return make_sim(chain_chunk=chunk or 0, **sched, **kw)
 
 
 def _raw(t):
     return t.detach().contiguous().view(torch.uint8).cpu()
 
 
-@pytest.mark.parametrize("label,shape,walls,extra,env", CASES, ids=[c[0] for c in CASES])
-def test_chain_chunk_length_changes_nothing(label, shape, walls, extra, env):
+@pytest.mark.parametrize("label,shape,walls,extra,sched", CASES, ids=[c[0] for c in CASES])
+def test_chain_chunk_length_changes_nothing(label, shape, walls, extra, sched):
     say(f"chain chunks: {label}")
     T = eos.temperature(0.7 if walls else 0.85)
     nz, ny, nx = shape
     kw = dict(nx=nx, ny=ny, nz=nz, T=T, walls_z=int(walls), **extra)
-    sims = [_sim(c, env, **kw) for c in (None, 1, 3, 8, 32, 64)]
+    sims = [_sim(c, sched, **kw) for c in (None, 1, 3, 8, 32, 64)]
     rho0 = droplet_rho(shape, T, walls=walls, radius=min(ny, nx) / 3.0)
     g = np.random.Generator(np.random.PCG64(9))
     u0 = torch.tensor(0.02 * g.uniform(-1, 1, (3,) + shape))

@@ -4,14 +4,13 @@ the same fixed order, so populations, density, momentum and the derived
 fields must agree bit for bit after every step, for every storage form, on
 grids smaller than a tile, ragged grids spanning several tiles and chunks,
 and walled boxes."""
-import os
-
 import numpy as np
 import pytest
 import torch
 
 from gpu_util import droplet_rho, make_sim, say
 from oracle import eos
+from paper_2504_03819_amd import lbfe
 
 pytestmark = pytest.mark.gpu
 
@@ -26,11 +25,7 @@ CASES = [
 
 
 def _sim(unfused, **kw):
-    os.environ["LBFE_FUSED"] = "0" if unfused else "1"
-    try:
-        return make_sim(**kw)
-    finally:
-        os.environ.pop("LBFE_FUSED", None)
+    return make_sim(step_path=lbfe.PATH_TWO_PASS if unfused else lbfe.PATH_FUSED, **kw)
 
 
 def _raw(t):

@@ -2,33 +2,22 @@
 which workgroup runs which tile: forced on and off at small sizes it must
 give the same states, fields, adjoint state and gradients bit for bit, on
 the two-read step, the fused step, the solid-mask path and the adjoint."""
-import os
-
 import numpy as np
 import pytest
 import torch
 
 from gpu_util import droplet_rho, make_sim, say
 from oracle import eos
-from paper_2504_03819_amd import inputs
+from paper_2504_03819_amd import inputs, lbfe
 
 pytestmark = pytest.mark.gpu
 
 OM = [1.0, 1.0, 1.0, 0.5] + [1.0] * 7
 
 
-def _sim(remap, env=None, **kw):
-    env = dict(env or {}, LBFE_XCD_REMAP=remap)
-    old = {k: os.environ.get(k) for k in env}
-    os.environ.update(env)
-    try:
-        return make_sim(**kw)
-    finally:
-        for k, v in old.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
+def _sim(remap, sched=None, **kw):
+    order = lbfe.ORDER_XCD if remap == "1" else lbfe.ORDER_ROUND_ROBIN
+    return make_sim(tile_order=order, **(sched or {}), **kw)
 
 
 def _raw(t):
@@ -36,24 +25,25 @@ def _raw(t):
 
 
 CASES = [
-    # (label, shape (nz, ny, nx), walls, extra, env)
-    ("periodic fp32 ragged", (40, 37, 70), False, dict(precision="fp32"), {}),
+    # (label, shape (nz, ny, nx), walls, extra, schedule)
+    ("periodic fp32 ragged", (40, 37, 70), False, dict(precision="fp32"), {"step_path": 1}),
     ("walls fp64 fused", (21, 26, 40), True, dict(precision="fp64", wet_mode=1, wet_value=1.3, omega=OM),
-     {"LBFE_FUSED": "1"}),
+     {"step_path": 2}),
+    ("periodic fp32 ragged fused", (40, 37, 70), False, dict(precision="fp32"), {"step_path": 2}),
     ("mask fp16dev", (14, 20, 23), False, dict(precision="fp16dev", wet_mode=2, wet_value=0.9, omega=OM, mask=True),
      {}),
 ]
 
 
-@pytest.mark.parametrize("label,shape,walls,extra,env", CASES, ids=[c[0] for c in CASES])
-def test_tile_order_changes_nothing(label, shape, walls, extra, env):
+@pytest.mark.parametrize("label,shape,walls,extra,sched", CASES, ids=[c[0] for c in CASES])
+def test_tile_order_changes_nothing(label, shape, walls, extra, sched):
     say(f"XCD tile order: {label}")
     T = eos.temperature(0.7 if walls or extra.get("mask") else 0.85)
     nz, ny, nx = shape
     kw = dict(nx=nx, ny=ny, nz=nz, T=T, walls_z=int(walls), **extra)
     if kw.pop("mask", False):
         kw["solid"] = inputs.mask_obstacles(shape)
-    sims = [_sim("0", env, **kw), _sim("1", env, **kw)]
+    sims = [_sim("0", sched, **kw), _sim("1", sched, **kw)]
     rho0 = droplet_rho(shape, T, walls=walls, radius=min(ny, nx) / 3.0)
     g = np.random.Generator(np.random.PCG64(3))
     u0 = torch.tensor(0.02 * g.uniform(-1, 1, (3,) + shape))
