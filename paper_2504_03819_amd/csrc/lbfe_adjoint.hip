@@ -285,7 +285,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     const Pops<P> fin(ft, kp);
     const Lam<real> lin(const_cast<void *>(lam_in), kp), lout(lam_out, kp);
 
-    // forward recomputation at x (identical to k_collide)
+    // forward recomputation at x: the moments, kinematics and collision of
+    // k_collide (the same device functions, so the same roundings)
     real k[27];
 #pragma unroll
     for (int i = 0; i < 27; ++i) k[i] = fin.ld(i, row, (unsigned)x);
@@ -294,11 +295,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     moments(k, rd, jx, jy, jz);
     const real *F = (const real *)b.F;
     const real Fx = F[n], Fy = F[kp.N + n], Fz = F[2 * (size_t)kp.N + n];
-    const real rho = (real)rd;
-    const real ux = (jx + (real)0.5 * Fx) / rho;
-    const real uy = (jy + (real)0.5 * Fy) / rho;
-    const real uz = (jz + (real)0.5 * Fz) / rho;
-    const real pm = (real)((1.0 + b.mu[n]) / 3.0);
+    const Kin<real> kin = kinematics(kp, rd, jx, jy, jz, Fx, Fy, Fz, b.mu[n]);
+    const real ux = kin.ux, uy = kin.uy, uz = kin.uz, pm = kin.pm;
     const real *Qa = (const real *)b.Q;
     const real q200 = Qa[n], q020 = Qa[kp.N + n], q002 = Qa[2 * (size_t)kp.N + n];
     real q220 = 0, q202 = 0, q022 = 0;
@@ -311,7 +309,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     Rates<real> R;
 #pragma unroll
     for (int q = 0; q < 11; ++q) R.w[q] = (real)kp.om[q];
-    const real om1 = (real)1 / (rho * (real)kp.nu / pm + (real)0.5);
+    const real om1 = kin.om1;
     R.w[1] = om1;
     cm_forward(k, ux, uy, uz);  // k: pre-collision central moments
     real ks[27];
@@ -458,14 +456,14 @@ template <int P> __global__ __launch_bounds__(ZCB) void k_adj_phi(KP kp, Bufs b,
         py *= 9.0;
         pz *= 9.0;
         const size_t n = (size_t)k * kp.plane + R.node;
-        // forward quantities at x (same arithmetic as the chain kernel)
+        // forward quantities at x, rounded as the chain kernel rounds them:
+        // u = (j + F/2) (1/rho), phi = c2 u with c2 = p_m - rho/3
         const double r = b.rho[n], mu = R.at(3, k, 0, 0);
-        const real rr = (real)r;
-        const double ux = (double)((j[n] + (real)0.5 * F[n]) / rr);
-        const double uy = (double)((j[N + n] + (real)0.5 * F[N + n]) / rr);
-        const double uz = (double)((j[2 * N + n] + (real)0.5 * F[2 * N + n]) / rr);
-        const double pm = (1.0 + mu) / 3.0;
-        const double c2 = pm - r / 3.0;
+        const real ir = (real)1 / (real)r;
+        const double ux = (double)((j[n] + (real)0.5 * F[n]) * ir);
+        const double uy = (double)((j[N + n] + (real)0.5 * F[N + n]) * ir);
+        const double uz = (double)((j[2 * N + n] + (real)0.5 * F[2 * N + n]) * ir);
+        const double c2 = (double)(real)((1.0 + mu - r) * (1.0 / 3.0));
         double pmb = A[A_PMB * N + n], rhob = A[A_RHOB * N + n];
         const double pu = px * ux + py * uy + pz * uz;
         pmb += pu;

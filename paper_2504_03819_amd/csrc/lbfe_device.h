@@ -342,17 +342,35 @@ __device__ inline void collide(real (&k)[27], const Rates<real> &R, real Fx, rea
 // omega_1 = 1/(rho nu/p_m + 1/2), CM transform, Eqs. (21)-(26), inverse
 // transform.  f: the arriving populations in, post-collision out.
 // ---------------------------------------------------------------------------
+// Node kinematics of Eqs. (11)-(12) and the rate after Eq. (26): u = (j +
+// F/2)/rho (as a product with 1/rho), p_m = (1 + mu)/3 and omega_1 =
+// 1/(rho nu/p_m + 1/2) in the form p_m/(rho nu + p_m/2).  Shared by the
+// collision and the adjoint's recomputation, so both see the same roundings.
+template <class real> struct Kin {
+    real rho, ux, uy, uz, pm, om1;
+};
+template <class real>
+__device__ inline Kin<real> kinematics(const KP &kp, double rd, real jx, real jy, real jz, real Fx, real Fy, real Fz,
+                                       double mu) {
+    Kin<real> q;
+    q.rho = (real)rd;
+    const real irho = (real)1 / q.rho;
+    q.ux = (jx + (real)0.5 * Fx) * irho;
+    q.uy = (jy + (real)0.5 * Fy) * irho;
+    q.uz = (jz + (real)0.5 * Fz) * irho;
+    q.pm = (real)((1.0 + mu) * (1.0 / 3.0));
+    q.om1 = q.pm / (q.rho * (real)kp.nu + (real)0.5 * q.pm);
+    return q;
+}
+
 template <class real>
 __device__ inline double collide_node(const KP &kp, real (&f)[27], double mu, real Fx, real Fy, real Fz, real q200,
                                       real q020, real q002) {
     double rd;
     real jx, jy, jz;
     moments(f, rd, jx, jy, jz);
-    const real rho = (real)rd, irho = (real)1 / rho;
-    const real ux = (jx + (real)0.5 * Fx) * irho;
-    const real uy = (jy + (real)0.5 * Fy) * irho;
-    const real uz = (jz + (real)0.5 * Fz) * irho;
-    const real pm = (real)((1.0 + mu) * (1.0 / 3.0));
+    const Kin<real> kin = kinematics(kp, rd, jx, jy, jz, Fx, Fy, Fz, mu);
+    const real ux = kin.ux, uy = kin.uy, uz = kin.uz, pm = kin.pm;
     real q220 = 0, q202 = 0, q022 = 0;
     if (kp.corr4) {  // Eq. (28)
         const real third = (real)(1.0 / 3.0);
@@ -363,7 +381,7 @@ __device__ inline double collide_node(const KP &kp, real (&f)[27], double mu, re
     Rates<real> R;
 #pragma unroll
     for (int k = 0; k < 11; ++k) R.w[k] = (real)kp.om[k];
-    R.w[1] = pm / (rho * (real)kp.nu + (real)0.5 * pm);  // 1 / (rho nu / p_m + 1/2)
+    R.w[1] = kin.om1;
 
     cm_forward(f, ux, uy, uz);
     collide(f, R, Fx, Fy, Fz, pm, q200, q020, q002, q220, q202, q022);

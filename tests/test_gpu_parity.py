@@ -6,7 +6,8 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import (DT, droplet_rho, gpu_fields, make_sim, oracle_fields, oracle_params, rel_err, say)
+from gpu_util import (DT, droplet_rho, fluid_slice, gpu_fields, make_sim, oracle_fields, oracle_params, rel_err,
+                      say)
 from oracle import eos, lbm
 from paper_2504_03819_amd import inputs, lbfe
 
@@ -77,28 +78,31 @@ def test_one_step_parity(label, shape, walls, extra):
 
 
 def test_trajectory_stationary_droplet_32():
-    """The 32^3 droplet at 0.9 Tc (radius 8, noise 1e-6): 60 steps, fields and
-    populations against the oracle; the full 500 steps run in the slow test."""
+    """The stationary-droplet workload: 32^3 at 0.9 Tc, radius 8, noise 1e-6,
+    its full 500 steps; fields and all 27 populations against the oracle
+    every 100 steps."""
     T = eos.temperature(0.9)
     sim = make_sim(nx=32, ny=32, nz=32, T=T)
     p = oracle_params(sim)
     rho0, _ = inputs.stationary_droplet(sim.rho_l, sim.rho_v)
     sim.init_density(torch.tensor(rho0))
     f = lbm.init(torch.tensor(rho0), p)
-    steps = 60
-    sim.step(steps)
-    f = lbm.run(f, p, steps)
-    g = gpu_fields(sim)
-    o = oracle_fields(f, p)
-    # a field that vanishes identically (F and Q on a one-node periodic box,
-    # where every link returns to the node) holds rounding residue on both
-    # sides: compare it absolutely
-    errs = {k: rel_err(g[k], o[k]) if float(o[k].abs().max()) > 1e-14 else float((g[k] - o[k]).abs().max())
-            for k in o}
-    errs["f"] = rel_err(sim.populations().cpu(), f)
-    say("droplet32 t=60: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
-    for k, v in errs.items():
-        assert v < TOL, (k, v)
+    for t in range(100, 501, 100):
+        sim.step(100)
+        f = lbm.run(f, p, 100)
+        g = gpu_fields(sim)
+        o = oracle_fields(f, p)
+        # a field that vanishes identically (F and Q on a one-node periodic
+        # box, where every link returns to the node) holds rounding residue on
+        # both sides: compare it absolutely
+        errs = {k: rel_err(g[k], o[k]) if float(o[k].abs().max()) > 1e-14 else float((g[k] - o[k]).abs().max())
+                for k in o}
+        fg = sim.populations().cpu()
+        errs["f"] = rel_err(fg, f)
+        errs["f_i"] = max(rel_err(fg[i], f[i]) for i in range(27))  # each direction on its own scale
+        say(f"droplet32 t={t}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+        for k, v in errs.items():
+            assert v < TOL, (t, k, v)
 
 
 def test_trajectory_sessile_droplet_walls():
@@ -297,6 +301,37 @@ def test_reductions_and_invariants():
             assert abs((r1[1 + a] - r[1 + a]) - r[4 + a]) < 1e-12
     fl = sim.fields()
     assert abs(float(fl["u"].norm(dim=0).max()) - r1[7]) < 1e-14
+
+
+@pytest.mark.parametrize("walls", [False, True], ids=["periodic", "walls"])
+def test_reductions_against_the_oracle(walls):
+    """lbfe_reduce (mass, momentum, total force, max |u|) against the same
+    sums of the oracle's fields of the same state: sums to 1e-12 of the sum
+    of magnitudes, the maximum to 1e-12."""
+    T = eos.temperature(0.7 if walls else 0.85)
+    shape = (18, 20, 22)
+    nz, ny, nx = shape
+    extra = dict(walls_z=1, wet_mode=lbfe.WET_PHI, wet_value=1.3, omega=[1.0, 1.0, 1.0, 0.5] + [1.0] * 7) \
+        if walls else {}
+    sim = make_sim(nx=nx, ny=ny, nz=nz, T=T, **extra)
+    p = oracle_params(sim)
+    rho0 = droplet_rho(shape, T, walls=walls, noise=1e-2, seed=12)
+    g = np.random.Generator(np.random.PCG64(14))
+    u0 = 0.03 * g.uniform(-1, 1, (3,) + shape)
+    sim.init_density(torch.tensor(rho0), torch.tensor(u0))
+    sim.step(7)
+    f = sim.populations().cpu()
+    A = lbm.aux_fields(f, p)
+    fl = fluid_slice(p)
+    rho, j, F, u = A["rho"][fl], A["j"][:, fl], A["F"][:, fl], A["u"][:, fl]
+    ref = [float(rho.sum())] + [float(j[a].sum()) for a in range(3)] + [float(F[a].sum()) for a in range(3)] \
+        + [float(u.norm(dim=0).max())]
+    scale = [float(rho.abs().sum())] + [float(j[a].abs().sum()) for a in range(3)] \
+        + [float(F[a].abs().sum()) for a in range(3)] + [ref[7]]
+    got = sim.reduce()
+    errs = [abs(a - b) / s for a, b, s in zip(got, ref, scale)]
+    say(f"reductions vs oracle ({'walls' if walls else 'periodic'}): max err {max(errs):.2e}")
+    assert max(errs) < 1e-12, list(zip(got, ref))
 
 
 def test_invalid_density_and_divergence_flag():

@@ -97,3 +97,46 @@ def test_contact_angle_error(form):
         th[f] = phys.contact_angle(sim.fields()["rho"].cpu().numpy(), sim.rho_l, sim.rho_v)[0]
     say(f"{form}: contact angle {th[form]:.3f} vs FP64 {th['fp64']:.3f} deg")
     assert abs(th[form] - th["fp64"]) < TOL[form][4]
+
+
+# one step of an FP16 state: the GPU's FP32 arithmetic and half rounding of
+# the result against the FP64 oracle stepping the same decoded state
+# (normwise, max |error| / max |f|): the rounding of the stored deviations
+# bounds it, a half ulp of h = f/w - 1 times w per population; with f0 in
+# FP32 that is a few 1e-7 of max f, with f0 in half up to 2^-12 h0 w0 / f0 =
+# 3.7e-4 at the 0.85 T_c liquid
+ONE_STEP_TOL = {"fp16dev_f0fp32": 2e-6, "fp16dev": 1e-3}
+
+
+@pytest.mark.parametrize("form", ["fp16dev_f0fp32", "fp16dev"])
+def test_fp16_one_step_against_the_oracle(form):
+    from gpu_util import oracle_params, rel_err
+    from oracle import lbm
+    T, rl, rv, rho0 = _droplet(24, 0.85, 7.0)
+    sim = make_sim(nx=24, ny=24, nz=24, T=T, precision=form)
+    sim.init_density(torch.tensor(rho0))
+    sim.step(10)
+    f_t = sim.populations().cpu()  # the decoded stored state
+    sim.step(1)
+    e = rel_err(sim.populations().cpu(), lbm.step(f_t, oracle_params(sim)))
+    say(f"{form}: one step vs oracle {e:.2e}")
+    assert e < ONE_STEP_TOL[form]
+
+
+@pytest.mark.parametrize("form", ["fp16dev_f0fp32", "fp16dev"])
+def test_fp16_full_size_spinodal_sampled(form):
+    """The 256^3 spinodal workload in the FP16 forms, 20 steps in: sampled
+    windows of the decoded state stepped by the FP64 oracle."""
+    from test_gpu_parity import _sampled_windows
+    n = 256
+    T = eos.temperature(0.8)
+    sim = make_sim(nx=n, ny=n, nz=n, T=T, precision=form, check_every=1000)
+    rho0, _ = inputs.spinodal(sim.rho_l, sim.rho_v)
+    sim.init_density(torch.tensor(rho0))
+    sim.step(20)
+    f_t = sim.populations()
+    sim.step(1)
+    f_t1 = sim.populations()
+    g = np.random.Generator(np.random.PCG64(16))
+    centres = [tuple(int(v) for v in g.integers(0, n, 3)) for _ in range(5)] + [(0, 0, 0)]
+    _sampled_windows(sim, f_t, f_t1, centres, ONE_STEP_TOL[form], f"256^3 spinodal {form}")
