@@ -236,6 +236,20 @@ int lbfe_set_populations(lbfe_ctx *ctx, const double *f_dev);
  * out[7] = max |u|.  Host array; synchronises. */
 int lbfe_reduce(lbfe_ctx *ctx, double out[8]);
 
+/* For callers that cannot allocate device memory or synchronise (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): lbfe_reduce with the result written asynchronously on the
+ * context's stream to out_dev (8 doubles, caller-owned device memory, same
+ * order), no host synchronisation, and the block partials in a static
+ * device scratch of 4 MiB that each GPU the library runs on holds until the
+ * process ends, instead of the workspace; it allocates nothing and calls no
+ * allocating routine.  The same kernels and summation order as lbfe_reduce,
+ * so the results are bit for bit the same.  Serves contexts of up to 2^24
+ * fluid nodes (E_INVAL beyond, checked first).  All calls on one GPU share
+ * its scratch: calls that overlap on one GPU (different streams or host
+ * threads) race. */
+int lbfe_reduce_into(lbfe_ctx *ctx, double *out_dev);
+
 /* ---- discrete adjoint (needs params.adjoint = 1) ----------------------- *
  * Not part of the paper's method: the exact reverse-mode derivative of the
  * discrete step above (the map f(t) -> f(t+1) of Sec. II B with the wall

@@ -621,6 +621,26 @@ int lbfe_reduce(lbfe_ctx *c, double out[8]) {
     return LBFE_OK;
 }
 
+int lbfe_reduce_into(lbfe_ctx *c, double *out_dev) {
+    if (!c) return LBFE_E_INVAL;
+    if (nblocks(c->kp.nfluid) > kScratchPartials) {
+        char buf[160];
+        std::snprintf(buf, sizeof buf, "lbfe_reduce_into serves up to %u fluid nodes (static scratch); use lbfe_reduce",
+                      kScratchPartials * (unsigned)kBlock);
+        return fail(c, LBFE_E_INVAL, buf);
+    }
+    int r = need_init(c);
+    if (r) return r;
+    if (!out_dev) return fail(c, LBFE_E_INVAL, "null output");
+    double *part = nullptr;
+    hipError_t e = scratch_partials(c->device, &part);
+    if (e != hipSuccess) return hip_fail(c, e, "reduce_into: scratch address");
+    e = launch_aux(c->stream, c->p.precision, c->kp, c->b, c->cur);
+    if (e == hipSuccess) e = launch_reduce_into(c->stream, c->p.precision, c->kp, c->b, part, out_dev);
+    if (e != hipSuccess) return hip_fail(c, e, "reduce_into");
+    return LBFE_OK;
+}
+
 int lbfe_adjoint_seed(lbfe_ctx *c, const double *dLdrho) {
     int r = need_bound(c);
     if (r) return r;

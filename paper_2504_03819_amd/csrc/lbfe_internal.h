@@ -13,6 +13,10 @@
 namespace lbfe {
 
 constexpr int kBlock = 256;  // threads per workgroup (4 wave64s)
+// allocation-free reduction: block partials the static scratch holds (up to
+// kScratchPartials * kBlock = 2^24 fluid nodes), and the devices it serves
+constexpr unsigned kScratchPartials = 1u << 16;
+constexpr int kMaxDevices = 64;
 
 // Kernel-side copy of the parameters, passed by value to every kernel.
 struct KP {
@@ -73,6 +77,11 @@ hipError_t launch_chain(hipStream_t s, int prec, const KP &kp, const Bufs &b);
 int chain_chunk_for(const KP &kp);
 hipError_t launch_export(hipStream_t s, int prec, const KP &kp, const Bufs &b, int which, double *out);
 hipError_t launch_reduce(hipStream_t s, int prec, const KP &kp, const Bufs &b);
+// the same reduction with the block partials in `part` (the static scratch
+// of lbfe_kernels.hip, from scratch_partials on the current device) and the
+// 8 results to `out`; hipErrorInvalidValue beyond kScratchPartials blocks
+hipError_t scratch_partials(int device, double **out);
+hipError_t launch_reduce_into(hipStream_t s, int prec, const KP &kp, const Bufs &b, double *part, double *out);
 hipError_t launch_get_pop(hipStream_t s, int prec, const KP &kp, const Bufs &b, const void *f, double *out);
 hipError_t launch_set_pop(hipStream_t s, int prec, const KP &kp, const Bufs &b, void *f, const double *in);
 hipError_t launch_check_rho0(hipStream_t s, const KP &kp, const double *rho0, int *flag);

@@ -15,11 +15,22 @@
 // (each x-row holds its 27 populations as 27 contiguous runs); one thread per
 // node, x fastest, so every population load and store of a wave64 is one
 // contiguous 64-element run.
+#include <mutex>
 #include <type_traits>
 
 #include "lbfe_device.h"
 
 namespace lbfe {
+
+// Scratch of the allocation-free reduction (lbfe_reduce_into): the block
+// partials of k_reduce_part, one record of 8 doubles per workgroup of
+// kBlock fluid nodes.  File-scope device memory that every GPU the library
+// runs on holds until the process ends; host code reaches it only through
+// the per-device address from hipGetSymbolAddress (the array's name is a
+// host-side stand-in, not a device address).  Every record a call reads is
+// written by that call first, so nothing needs clearing between calls.
+static __device__ __align__(256) double scratch[8 * (size_t)kScratchPartials];
+
 namespace {
 
 template <int P> using real_t = typename Pol<P>::real;
@@ -452,6 +463,32 @@ hipError_t launch_reduce(hipStream_t s, int prec, const KP &kp, const Bufs &b) {
         constexpr int P = decltype(pc)::value;
         k_reduce_part<P><<<g, kBlock, 0, s>>>(kp, b.rho, b.j, b.F, b.nbr, b.part);
         k_reduce_final<<<1, kBlock, 0, s>>>(g, b.part, b.red);
+        return hipGetLastError();
+    });
+}
+
+hipError_t scratch_partials(int device, double **out) {
+    static std::mutex mu;
+    static double *ptr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[device] = (double *)p;
+    }
+    *out = ptr[device];
+    return hipSuccess;
+}
+
+hipError_t launch_reduce_into(hipStream_t s, int prec, const KP &kp, const Bufs &b, double *part, double *out) {
+    const unsigned g = nblocks(kp.nfluid);
+    if (g > kScratchPartials) return hipErrorInvalidValue;
+    return dispatch(prec, [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        k_reduce_part<P><<<g, kBlock, 0, s>>>(kp, b.rho, b.j, b.F, b.nbr, part);
+        k_reduce_final<<<1, kBlock, 0, s>>>(g, part, out);
         return hipGetLastError();
     });
 }

@@ -76,6 +76,7 @@ def lib():
         "lbfe_get_populations": (c_int, [V, V]),
         "lbfe_set_populations": (c_int, [V, V]),
         "lbfe_reduce": (c_int, [V, POINTER(c_double)]),
+        "lbfe_reduce_into": (c_int, [V, V]),
         "lbfe_adjoint_seed": (c_int, [V, V]),
         "lbfe_adjoint_step": (c_int, [V, V]),
         "lbfe_adjoint_seed_populations": (c_int, [V, V]),
@@ -262,6 +263,15 @@ class Simulation:
         out = (c_double * 8)()
         self._check(lib().lbfe_reduce(self._ctx, out))
         return list(out)
+
+    def reduce_into(self, out):
+        """lbfe_reduce_into: the 8 reductions into the device tensor `out`
+        (float64, 8 elements), asynchronously; no allocation."""
+        torch = self._torch
+        if out.dtype != torch.float64 or out.numel() < 8 or not out.is_contiguous() or out.device != self.device:
+            raise ValueError("out must be a contiguous float64 device tensor of >= 8 elements on the context's device")
+        self._check(lib().lbfe_reduce_into(self._ctx, _ptr(out)))
+        return out
 
     # ------------------------------------------------------------ adjoint --
     def adjoint_seed(self, dL_drho):
