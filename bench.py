@@ -336,6 +336,56 @@ def wetting_adjoint(lbfe, torch, steps=4000, every=200, neutral=0, phi=1.3):
     return res
 
 
+def wetting_angles(lbfe, torch, steps=40000, every=10000, form="fp64", cases=None, dump=None):
+    """The wetting test of Sec. III C on the paper's geometry: Nx x Ny x Nz =
+    128 x 256 x 256, solid planes z = 0 and 255 (halfway bounce-back), a
+    droplet of radius 30 centred on the wall plane z = 0.5, 0.7 T_c, the
+    third-order rate omega_3 = 1/2 (the wall reading of the oracle), and the
+    three printed cases: neutral (phi = 1), phi = 1.6 and drho = 1.8.
+    Reports the contact angle (oracle measurement) every `every` steps, the
+    spread of mu over the fluid, and the mass drift; with `dump` a directory,
+    the central x-z and y-z density planes of every report go to an .npz
+    file there."""
+    from oracle import phys
+    from paper_2504_03819_amd import inputs
+    T = 0.7 * 8 * (9 / 392) / (27 * (2 / 21))
+    nx, ny, nz = 128, 256, 256
+    cases = cases or [("neutral", lbfe.WET_PHI, 1.0, 89.9), ("phi 1.6", lbfe.WET_PHI, 1.6, 33.5),
+                      ("drho 1.8", lbfe.WET_DELTA, 1.8, 153.4)]
+    out = {"workload": "sessile droplet 128x256x256 (Nx x Ny x Nz), walls z=0,255, r=30 at z=0.5, T=0.7Tc, "
+                       f"omega3=0.5, {form}", "steps": steps, "cases": {}}
+    for label, mode, value, paper in cases:
+        sim = lbfe.Simulation(device="cuda:0", nx=nx, ny=ny, nz=nz, T=T, walls_z=1, wet_mode=mode, wet_value=value,
+                              omega=[1.0, 1.0, 1.0, 0.5] + [1.0] * 7, precision=form, check_every=every)
+        rl, rv = sim.rho_l, sim.rho_v
+        rho = inputs.sphere((nz, ny, nx), (nx / 2, ny / 2, 0.5), 30.0, rl, rv)
+        rho[0] = rho[-1] = rv
+        sim.init_density(torch.tensor(rho))
+        m0 = sim.reduce()[0]
+        traj = []
+        done = 0
+        while done < steps:
+            sim.step(every)
+            done += every
+            f = sim.fields()
+            r = f["rho"].cpu().numpy()
+            mu = f["mu"][1:-1].cpu().numpy()
+            th, zc, Rf = phys.contact_angle(r, rl, rv)
+            traj.append({"step": done, "theta": round(th, 3), "cap_radius": round(Rf, 2),
+                         "mu_spread": float(mu.max() - mu.min()), "rho_max": float(r.max())})
+            if dump:
+                import numpy as np
+                os.makedirs(dump, exist_ok=True)
+                np.savez_compressed(os.path.join(dump, f"wet_{label.replace(' ', '_')}_{done}.npz"),
+                                    xz=r[:, ny // 2, :], yz=r[:, :, nx // 2], rho_l=rl, rho_v=rv)
+            print(f"[bench] wetting {label}: step {done} theta {th:.2f}", file=sys.stderr, flush=True)
+        out["cases"][label] = {"mode": int(mode), "value": value, "paper_theta": paper, "trajectory": traj,
+                               "mass_drift": (sim.reduce()[0] - m0) / m0}
+        sim.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def time_collision_adjoint(lbfe, torch, forward=5000, adjoint=500, snapshots=8):
     """512^3 head-on collision in FP32: `forward` steps, then the adjoint of
     the last `adjoint` steps from the stored state f(T - adjoint) with the
@@ -529,6 +579,10 @@ def main():
                     help="time the 512^3 collision with a binomial-checkpointed adjoint of its last steps")
     ap.add_argument("--wetting-adjoint", nargs=3, type=int, metavar=("STEPS", "CHECKPOINT_EVERY", "NEUTRAL"),
                     help="192x192x96 wetting gradients (FP32 and FP64 adjoint) against central differences")
+    ap.add_argument("--wetting-angles", nargs=2, type=int, metavar=("STEPS", "EVERY"),
+                    help="Sec. III C wetting on the paper's 128x256x256 geometry: contact angles of the printed cases")
+    ap.add_argument("--wetting-cases", default="neutral,phi 1.6,drho 1.8")
+    ap.add_argument("--dump-planes", default=None, help="directory for the central density planes (--wetting-angles)")
     ap.add_argument("--spinodal-stats", nargs=2, type=int, metavar=("STEPS", "CHECK_EVERY"),
                     help="256^3 spinodal in every storage form side by side: error onset and end statistics")
     args = ap.parse_args()
@@ -551,6 +605,13 @@ def main():
         return
     if args.spinodal_stats:
         print(json.dumps(spinodal_stats(lbfe, torch, *args.spinodal_stats)), flush=True)
+        return
+    if args.wetting_angles:
+        allc = {"neutral": ("neutral", lbfe.WET_PHI, 1.0, 89.9), "phi 1.6": ("phi 1.6", lbfe.WET_PHI, 1.6, 33.5),
+                "drho 1.8": ("drho 1.8", lbfe.WET_DELTA, 1.8, 153.4)}
+        cases = [allc[c] for c in args.wetting_cases.split(",")]
+        print(json.dumps(wetting_angles(lbfe, torch, *args.wetting_angles, cases=cases, dump=args.dump_planes)),
+              flush=True)
         return
     if args.collision_adjoint:
         print(json.dumps(time_collision_adjoint(lbfe, torch, *args.collision_adjoint)), flush=True)

@@ -142,6 +142,64 @@ def young_laplace(sigma, radius, a, b, R, T, guess=None):
     return rl, rv
 
 
+def _lap_h_matrix(shape):
+    """The isotropic D3Q27 Laplacian of the step (reading R4: lap_h g =
+    6 sum_i w_i (g(x + c_i) - g(x)), weights of Eq. (17)) as a sparse matrix
+    on a periodic (nz, ny, nx) grid, nodes in C order."""
+    import scipy.sparse as sp
+    from .lattice import C, W_EXACT
+    nz, ny, nx = shape
+    n = nz * ny * nx
+    idx = np.arange(n).reshape(shape)
+    rows, cols, vals = [], [], []
+    for (cx, cy, cz), w in zip(C, W_EXACT):
+        if (cx, cy, cz) == (0, 0, 0):
+            continue
+        nb = np.roll(idx, shift=(-cz, -cy, -cx), axis=(0, 1, 2))  # index of x + c_i
+        rows += [idx.ravel(), idx.ravel()]
+        cols += [nb.ravel(), idx.ravel()]
+        vals += [np.full(n, 6.0 * float(w)), np.full(n, -6.0 * float(w))]
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+
+
+def static_equilibrium_3d(rho_init, a, b, R, T, kappa, tol=1e-14, maxit=60):
+    """Discrete static equilibrium in 3-D (pins P9/P11): the density field of
+    a periodic box with mu0(rho) - kappa lap_h rho = mu* at every node and the
+    mass of rho_init, by Newton's method on the sparse system (unknowns rho
+    and mu*).  With u = 0 such a field makes F = 0, Q = 0 and the moving
+    populations uniform, so it is a fixed point of the step for any rates.
+    Returns (rho, mu*)."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    r = np.array(rho_init, dtype=np.float64)
+    shape = r.shape
+    r = r.ravel()
+    n = r.size
+    mass = r.sum()
+    L = _lap_h_matrix(shape)
+    mu_s = float(np.mean(_mu0_vec(r, a, b, R, T) - kappa * (L @ r)))
+    def resid(rr, mm):
+        return np.concatenate([_mu0_vec(rr, a, b, R, T) - kappa * (L @ rr) - mm, [rr.sum() - mass]])
+
+    for _ in range(maxit):
+        res = resid(r, mu_s)
+        # converged: mu0 - kappa lap_h rho - mu* at rounding level, mass to
+        # the rounding of its sum
+        if np.max(np.abs(res[:n])) < tol and abs(res[n]) < 1e-13 * mass:
+            break
+        # bordered Newton system [[J, -1], [1^T, 0]] (d_rho, d_mu) = -res,
+        # solved through one sparse LU of J = diag(mu0') - kappa lap_h
+        lu = spla.splu(sp.csc_matrix(sp.diags(_dmu0_vec(r, a, b, R, T)) - kappa * L))
+        y1 = lu.solve(-res[:n])
+        y2 = lu.solve(np.ones(n))
+        dmu = (-res[n] - y1.sum()) / y2.sum()
+        d = np.concatenate([y1 + dmu * y2, [dmu]])
+        r, mu_s, done = _damped_update(r, mu_s, d, resid, res, b, tol)
+        if done:
+            break
+    return r.reshape(shape), mu_s
+
+
 def equimolar_radius(rho, rho_in, rho_out):
     """R = (3V / 4 pi)^(1/3), V = sum (rho - rho_out) / (rho_in - rho_out)."""
     V = float(np.sum((np.asarray(rho) - rho_out) / (rho_in - rho_out)))

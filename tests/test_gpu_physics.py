@@ -199,17 +199,52 @@ def test_moving_walls_droplet_keeps_its_shape():
     assert drift < 1e-10
 
 
+P15_NOT_REPRODUCED = ("the wetting reading here (window and limiter of Eq. (38) on the contact-line nodes only, the "
+                      "solid density in the isotropic Laplacian) gives {}; the paper prints {}")
+
+
+@pytest.mark.parametrize("label,mode,value,paper,steps", [
+    ("neutral", lbfe.WET_PHI, 1.0, 89.9, 20000),
+    pytest.param("phi 1.6", lbfe.WET_PHI, 1.6, 33.5, 30000, marks=pytest.mark.xfail(
+        strict=True, reason=P15_NOT_REPRODUCED.format("30.3 deg (cap radius 95, measurement robust to the fit's "
+                                                      "cut-off height)", "33.5 deg"))),
+    pytest.param("drho 1.8", lbfe.WET_DELTA, 1.8, 153.4, 10000, marks=pytest.mark.xfail(
+        strict=True, reason=P15_NOT_REPRODUCED.format("no attached state: the droplet leaves the wall within 2000 "
+                                                      "steps and evaporates", "153.4 deg"))),
+])
+def test_contact_angle_paper_geometry(label, mode, value, paper, steps):
+    """Sec. III C on the paper's geometry: Nx x Ny x Nz = 128 x 256 x 256,
+    solid planes z = 0 and 255, a droplet of radius 30 centred on the wall
+    plane, 0.7 T_c (omega_3 = 1/2, the wall reading of the oracle), FP32
+    storage (angles agree with FP64 to 1e-3 deg).  The printed angles within
+    2 deg, mu uniform over the fluid."""
+    from oracle import phys as ph
+    T = eos.temperature(0.7)
+    nx, ny, nz = 128, 256, 256
+    sim = make_sim(nx=nx, ny=ny, nz=nz, T=T, walls_z=1, wet_mode=mode, wet_value=value, omega=WALL_OMEGA,
+                   precision="fp32", check_every=5000)
+    rho0 = inputs.sphere((nz, ny, nx), (nx / 2, ny / 2, 0.5), 30.0, sim.rho_l, sim.rho_v)
+    rho0[0] = rho0[-1] = sim.rho_v
+    sim.init_density(torch.tensor(rho0))
+    sim.step(steps)
+    f = sim.fields()
+    rho, mu = f["rho"].cpu().numpy(), f["mu"].cpu().numpy()[1:-1]
+    th, zc, Rf = ph.contact_angle(rho, sim.rho_l, sim.rho_v)
+    say(f"contact angle {label}: theta={th:.2f} deg (paper {paper}), cap radius {Rf:.1f}, "
+        f"mu spread {mu.max() - mu.min():.1e}")
+    assert abs(th - paper) <= 2.0
+    assert mu.max() - mu.min() < 2e-3
+
+
 @pytest.mark.parametrize("mode,value,lo,hi", [
-    (lbfe.WET_NEUTRAL, 1.0, 89.0, 91.5),
-    (lbfe.WET_PHI, 1.6, 28.0, 34.0),
     (lbfe.WET_PHI, 1.3, 55.0, 61.0),
     (lbfe.WET_DELTA, 0.9, 116.0, 123.0),
 ])
-def test_contact_angle(mode, value, lo, hi):
-    """Sec. III C: sessile droplet (radius 32 on a 192x192x96 box with solid
-    planes at z = 0, 95) at 0.7 T_c.  Neutral wetting gives 90 deg; phi > 1
-    makes the wall hydrophilic (phi = 1.6: the paper reports 33.5 deg on a
-    128x256x256 box), drho > 0 hydrophobic; mu becomes uniform."""
+def test_contact_angle_calibration(mode, value, lo, hi):
+    """Calibration points of the wetting workload (192x192x96, radius 32,
+    0.7 T_c; no printed values in the paper: these angles were measured
+    here and are kept as regression windows for the target angles 60 and
+    120 deg)."""
     from oracle import phys as ph
     T = eos.temperature(0.7)
     sim = make_sim(nx=192, ny=192, nz=96, T=T, walls_z=1, wet_mode=mode, wet_value=value, omega=WALL_OMEGA,
@@ -220,7 +255,8 @@ def test_contact_angle(mode, value, lo, hi):
     f = sim.fields()
     rho, mu = f["rho"].cpu().numpy(), f["mu"].cpu().numpy()[1:-1]
     th, zc, Rf = ph.contact_angle(rho, sim.rho_l, sim.rho_v)
-    say(f"contact angle mode={mode} value={value}: theta={th:.2f} deg (cap radius {Rf:.1f}), mu spread {mu.max() - mu.min():.1e}")
+    say(f"contact angle mode={mode} value={value}: theta={th:.2f} deg (cap radius {Rf:.1f}), "
+        f"mu spread {mu.max() - mu.min():.1e}")
     assert lo <= th <= hi
     assert mu.max() - mu.min() < 1e-3
 
@@ -262,3 +298,32 @@ def test_droplet_on_pillars_cassie_or_wenzel(label, mode, value):
     else:
         assert frac > 0.2 and zc < top + 8
     assert drift < 1e-10
+
+
+def test_lb_droplet_converges_to_the_newton_equilibrium():
+    """Pin P11: a 16^3 droplet at 0.7 T_c (tanh, radius 5) stepped by the
+    GPU FP64 path relaxes to the discrete static equilibrium that Newton's
+    method finds for the same mass (oracle.phys.static_equilibrium_3d):
+    after 4e4 steps the density fields agree to 1e-8 of rho_l - rho_v and
+    the velocity has decayed to rounding."""
+    from oracle import phys as ph
+    n = 16
+    T = eos.temperature(0.7)
+    sim = make_sim(nx=n, ny=n, nz=n, T=T, check_every=10000)
+    rl, rv = sim.rho_l, sim.rho_v
+    rho0 = ph.tanh_droplet((n, n, n), (n / 2, n / 2, n / 2), 5.0, rl, rv)
+    r_newton, mu_star = ph.static_equilibrium_3d(rho0, eos.PAPER["a"], eos.PAPER["b"], eos.PAPER["R"], T, 0.02)
+    sim.init_density(torch.tensor(rho0))
+    errs = []
+    for _ in range(2):
+        sim.step(20000)
+        f = sim.fields()
+        e = float(np.abs(f["rho"].cpu().numpy() - r_newton).max()) / (rl - rv)
+        errs.append(e)
+    umax = float(f["u"].abs().max())
+    say(f"LB vs Newton droplet 16^3: rho err every 2e4 steps {['%.1e' % v for v in errs]}, max|u| {umax:.1e}, "
+        f"mu - mu* {float((f['mu'] - mu_star).abs().max()):.1e}")
+    # (measured: 6.6e-12 at 2e4 and 4e4 steps; beyond 5e4 steps a slow mode
+    # of this small box grows from rounding, 1.9e-10 at 6e4 and 5e-4 at 1e5)
+    assert errs[-1] < 1e-8
+    assert umax < 1e-10
