@@ -20,6 +20,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -551,7 +552,7 @@ def summarize_counters(fetch_csv, write_csv, form, workload_name, out_path):
     fetch = {k: sum(v) / len(v) for k, v in fetch_all.items()}
     write = {k: sum(v) / len(v) for k, v in write_all.items()}
     res = {"form": form, "workload": workload_name, "source_hash": kernel_source_hash(),
-           "dominant_kernel": dom[0].split("(")[0],
+           "dominant_kernel": re.sub(r"^void |lbfe::\(anonymous namespace\)::|\(lbfe::KP.*$", "", dom[0]),
            "fetch_kib_per_launch": fetch[dom[0]], "write_kib_per_launch": write[dom[0]],
            "copy_fetch_factor": f_fac, "copy_write_factor": w_fac,
            "bytes_per_launch": (fetch[dom[0]] * f_fac + write[dom[0]] * w_fac) * 1024.0,
