@@ -28,17 +28,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
-POP_BYTES = {"fp64": 8, "fp32": 4, "fp16dev": 2, "fp16dev_f0fp32": 2}
+POP_BYTES = {"fp64": 8, "fp32": 4, "fp16dev": 2, "fp16dev_f0fp32": 2, "fp64_state": 8, "fp32_state": 4}
 METRIC = "MLUPS and % of HBM peak, D3Q27 fused step FP64 vs FP32/FP16-store; adjoint MLUPS"
 COUNTERS = os.path.join(ROOT, "profiles", "collide_counters.json")
 
 
 def alg_bytes_per_node(form):
     """Method state read once and written once: 27 populations each way
-    (FP16 with f0 in FP32: 26 halves + 1 float)."""
+    (FP16 with f0 in FP32: 26 halves + 1 float); in the moment-state forms
+    (`*_state`, every rate but omega_1 at 1) the 16 post-collision numbers
+    each way."""
     if form == "fp16dev_f0fp32":
         return 2 * (26 * 2 + 4)
+    if form.endswith("_state"):
+        return 32 * POP_BYTES[form]
     return 54 * POP_BYTES[form]
+
+
+def form_params(form):
+    """Simulation keywords of a bench form: a storage form, with `_state`
+    the moment-state step path."""
+    if form.endswith("_state"):
+        return dict(precision=form[:-len("_state")], step_path=3)
+    return dict(precision=form)
 
 
 def kernel_source_hash():
@@ -58,7 +70,11 @@ def kernel_source_hash():
 # form rounds the rest population, which carries the density contrast: mass
 # drifts by 5.9e-2 per 1000 steps and long runs leave the EOS domain)
 INVALID_FORMS = {"fp16dev": "all-FP16 storage: mass drift 5.9e-2 per 1000 steps, diverges in long runs"}
-STEP_KERNELS = ("k_moments", "k_chain", "k_collide", "k_fused", "k_wall_rho", "k_wall_move")
+STEP_KERNELS = ("k_moments", "k_chain", "k_collide", "k_fused", "k_wall_rho", "k_wall_move", "k_mstate")
+PATH_NAMES = {1: "two-pass", 2: "fused", 3: "state"}
+DOMINANT = {"two-pass": "k_collide (collide + push-stream)",
+            "fused": "k_fused (collide + stream + next-step moments)",
+            "state": "k_mstate<kCollide> (rebuild from the 16-number state, gather, collide, new state)"}
 
 
 def workload(name, lbfe, torch):
@@ -115,7 +131,7 @@ def workload(name, lbfe, torch):
 
 
 def time_form(lbfe, torch, geom, rho, u, form, steps, warmup, timed_steps):
-    sim = lbfe.Simulation(device="cuda:0", precision=form, **geom)
+    sim = lbfe.Simulation(device="cuda:0", **form_params(form), **geom)
     nfluid = sim.params.nx * sim.params.ny * (sim.params.nz - (2 if sim.params.walls_z else 0))
     if geom.get("solid") is not None:
         nfluid = int((geom["solid"] == 0).sum())
@@ -131,7 +147,7 @@ def time_form(lbfe, torch, geom, rho, u, form, steps, warmup, timed_steps):
     ms = e0.elapsed_time(e1)
     kms = sim.step_timed(timed_steps)
     kavg = {k: v / timed_steps for k, v in kms.items()}
-    path = "fused" if sim.params.step_path == lbfe.PATH_FUSED else "two-pass"
+    path = PATH_NAMES[sim.params.step_path]
     mlups = nfluid * steps / (ms / 1e3) / 1e6
     b_alg = alg_bytes_per_node(form)
     out = {
@@ -337,6 +353,113 @@ def wetting_adjoint(lbfe, torch, steps=4000, every=200, neutral=0, phi=1.3):
     return res
 
 
+def wetting_fd_table(lbfe, torch, steps=4000, every=200):
+    """The wetting workload's gradient check at the five target angles (30,
+    60, 90, 120, 150 deg: phi 1.62, 1.28, 1.0 and drho 0.9, 1.5 on the
+    192x192x96 box, walls, 0.7 T_c, omega3 = 1/2): dL/dkappa, dL/d(wet) and
+    dL/drho0 at three nodes from the hand-written adjoint (FP32 and FP64),
+    against central differences of the FP64 forward.  The wetting rule of
+    Eq. (38) switches branches where a wall node's average density crosses a
+    window edge or the limiter binds; a difference quotient is the adjoint's
+    derivative only if both probes take the same branches at every step.  So
+    each probe records, per step, a fingerprint of its active set (which wall
+    nodes are in the window and which are clamped), and a difference is
+    reported only where the +h and -h fingerprints agree at every step;
+    elsewhere the number of steps whose active sets differ is reported."""
+    import numpy as np
+    from paper_2504_03819_amd import autograd as lag, inputs
+    geom, rho, u, desc = workload("wetting", lbfe, torch)
+    T, om = geom["T"], geom["omega"]
+    rl, rv = lbfe.coexistence(9 / 392, 2 / 21, 1.0, T)
+    lo, hi = 0.05 * rl + 0.95 * rv, 0.95 * rl + 0.05 * rv
+    kappa, dev = 0.02, "cuda:0"
+    nx, ny, nz = 192, 192, 96
+    g = np.random.Generator(np.random.PCG64(41))
+    wts = torch.tensor(g.uniform(0.5, 1.5, (4, ny, nx)), device=dev)
+    w1 = torch.tensor([1 / 6, 2 / 3, 1 / 6], dtype=torch.float64, device=dev)
+
+    def fingerprint(r, mode, value):
+        out = 0.0
+        for k, z in enumerate((1, nz - 2)):
+            pl = r[z]
+            ave = sum(w1[a] * w1[b] * torch.roll(pl, shifts=(1 - a, 1 - b), dims=(0, 1))
+                      for a in range(3) for b in range(3))
+            win = (ave >= lo) & (ave <= hi)
+            v = value * ave if mode == lbfe.WET_PHI else ave - value
+            clamp = win & ((v < lo) | (v > hi))
+            out += float((wts[2 * k] * win).sum() + (wts[2 * k + 1] * clamp).sum())
+        return out
+
+    def forward64(mode, value, k=kappa, r0=None, record=False):
+        sim = lbfe.Simulation(device=dev, nx=nx, ny=ny, nz=nz, T=T, walls_z=1, wet_mode=mode, wet_value=value,
+                              kappa=k, omega=om, check_every=steps)
+        sim.init_density(torch.tensor(rho if r0 is None else r0))
+        fp = []
+        if record:
+            for _ in range(steps):
+                fp.append(fingerprint(sim.field(lbfe.FIELD_RHO), mode, value))
+                sim.step(1)
+        else:
+            sim.step(steps)
+        out = sim.fields()["rho"]
+        sim.close()
+        return out, fp
+
+    cases = [(30, lbfe.WET_PHI, 1.62), (60, lbfe.WET_PHI, 1.28), (90, lbfe.WET_PHI, 1.0), (120, lbfe.WET_DELTA, 0.9),
+             (150, lbfe.WET_DELTA, 1.5)]
+    nodes = [(48, 96, 96), (33, 96, 96), (80, 96, 96)]
+    res = {"workload": desc + f", {steps} steps, checkpoints every {every}", "nodes_zyx": nodes, "cases": []}
+    for angle, mode, value in cases:
+        dv = 0.05 if mode == lbfe.WET_PHI else 0.1
+        tgt = forward64(mode, value + dv)[0] + torch.tensor(
+            1e-3 * (rl - rv) * inputs.uniform_noise(rho.shape, 1.0, 21), device=dev)
+
+        def loss(rT):
+            return float(((rT - tgt)[1:-1] ** 2).sum())
+
+        row = {"target_angle": angle, "mode": int(mode), "value": value}
+        for form in ("fp32", "fp64"):
+            cfg = lag.StepConfig(nx=nx, ny=ny, nz=nz, steps=steps, checkpoint_every=every, T=T, walls_z=1,
+                                 wet_mode=mode, precision=form, omega=om, device=dev, keep_aux=form == "fp32")
+            r0 = torch.tensor(rho, device=dev, requires_grad=True)
+            kap = torch.tensor(kappa, dtype=torch.float64, requires_grad=True)
+            wet = torch.tensor(value, dtype=torch.float64, requires_grad=True)
+            L = ((lag.simulate(r0, kap, wet, cfg) - tgt)[1:-1] ** 2).sum()
+            L.backward()
+            row[form] = {"dL_dkappa": float(kap.grad), "dL_dwet": float(wet.grad),
+                         "dL_drho0": [float(r0.grad[z, y, x]) for z, y, x in nodes]}
+            del r0, L
+            torch.cuda.empty_cache()
+
+        def central(h, **kw):
+            (rp, fpp), (rm, fpm) = (forward64(record=True, **{k: v(s) for k, v in kw.items()}) for s in (1, -1))
+            crossings = sum(1 for a, b in zip(fpp, fpm) if a != b)
+            return (loss(rp) - loss(rm)) / (2 * h), crossings
+
+        fd = {}
+        hk, hw, hr = 2e-6, 1e-5, 1e-4
+        fd["kappa"] = central(hk, mode=lambda s: mode, value=lambda s: value, k=lambda s: kappa + s * hk)
+        fd["wet"] = central(hw, mode=lambda s: mode, value=lambda s: value + s * hw)
+        fd["rho0"] = []
+        for z, y, x in nodes:
+            def r0_of(sgn, z=z, y=y, x=x):
+                r = rho.copy()
+                r[z, y, x] += sgn * hr
+                return r
+            fd["rho0"].append(central(hr, mode=lambda s: mode, value=lambda s: value, r0=r0_of))
+        row["fd_fp64"] = {"kappa": fd["kappa"][0], "wet": fd["wet"][0], "rho0": [v[0] for v in fd["rho0"]]}
+        row["active_set_crossings"] = {"kappa": fd["kappa"][1], "wet": fd["wet"][1], "rho0": [v[1] for v in fd["rho0"]]}
+        for form in ("fp32", "fp64"):
+            gr = row[form]
+            rel = {"kappa": abs(gr["dL_dkappa"] - fd["kappa"][0]) / abs(fd["kappa"][0]),
+                   "wet": abs(gr["dL_dwet"] - fd["wet"][0]) / abs(fd["wet"][0]) if fd["wet"][0] else None,
+                   "rho0": [abs(a - b[0]) / abs(b[0]) for a, b in zip(gr["dL_drho0"], fd["rho0"])]}
+            row[form]["rel_err_vs_fd"] = rel
+        res["cases"].append(row)
+        print(f"[bench] fd table: {angle} deg done", file=sys.stderr, flush=True)
+    return res
+
+
 def wetting_angles(lbfe, torch, steps=40000, every=10000, form="fp64", cases=None, dump=None):
     """The wetting test of Sec. III C on the paper's geometry: Nx x Ny x Nz =
     128 x 256 x 256, solid planes z = 0 and 255 (halfway bounce-back), a
@@ -538,11 +661,13 @@ def summarize_counters(fetch_csv, write_csv, form, workload_name, out_path):
     --pmc passes (FETCH_SIZE, then WRITE_SIZE) of
     `bench.py --copy-calib --forms <form> --no-cpu-baseline --no-adjoint`;
     the dominant kernel is the fused collide-stream kernel if the run has
-    one, else the two-pass collide-stream kernel."""
+    one, else the moment-state collide pass, else the two-pass
+    collide-stream kernel."""
     fetch_all = _read_counter_csv(fetch_csv, "FETCH_SIZE")
     write_all = _read_counter_csv(write_csv, "WRITE_SIZE")
     copy_k = [k for k in fetch_all if "copybuffer" in k.lower()]
-    dom = [k for k in fetch_all if "k_fused" in k] or [k for k in fetch_all if "k_collide" in k]
+    dom = [k for k in fetch_all if "k_fused" in k] or [k for k in fetch_all if re.search(r"k_mstate<\d+, 2,", k)] \
+        or [k for k in fetch_all if "k_collide" in k]
     if not copy_k or not dom:
         raise SystemExit(f"kernels not found: {sorted(fetch_all)}")
     # the 1 GiB copies are the largest copy dispatches of the run
@@ -583,6 +708,8 @@ def main():
     ap.add_argument("--wetting-angles", nargs=2, type=int, metavar=("STEPS", "EVERY"),
                     help="Sec. III C wetting on the paper's 128x256x256 geometry: contact angles of the printed cases")
     ap.add_argument("--wetting-cases", default="neutral,phi 1.6,drho 1.8")
+    ap.add_argument("--wetting-fd-table", nargs=2, type=int, metavar=("STEPS", "CHECKPOINT_EVERY"),
+                    help="adjoint vs central differences at the five target angles, with the active-set check")
     ap.add_argument("--dump-planes", default=None, help="directory for the central density planes (--wetting-angles)")
     ap.add_argument("--spinodal-stats", nargs=2, type=int, metavar=("STEPS", "CHECK_EVERY"),
                     help="256^3 spinodal in every storage form side by side: error onset and end statistics")
@@ -607,6 +734,9 @@ def main():
     if args.spinodal_stats:
         print(json.dumps(spinodal_stats(lbfe, torch, *args.spinodal_stats)), flush=True)
         return
+    if args.wetting_fd_table:
+        print(json.dumps(wetting_fd_table(lbfe, torch, *args.wetting_fd_table)), flush=True)
+        return
     if args.wetting_angles:
         allc = {"neutral": ("neutral", lbfe.WET_PHI, 1.0, 89.9), "phi 1.6": ("phi 1.6", lbfe.WET_PHI, 1.6, 33.5),
                 "drho 1.8": ("drho 1.8", lbfe.WET_DELTA, 1.8, 153.4)}
@@ -630,8 +760,7 @@ def main():
         results[form] = time_form(lbfe, torch, geom, rho, u, form, args.steps, args.warmup, args.timed_steps)
     head = forms[0]
     r = results[head]
-    dom = "k_fused (collide + stream + next-step moments)" if r["step_path"] == "fused" \
-        else "k_collide (collide + push-stream)"
+    dom = DOMINANT[r["step_path"]]
     roof = {
         "bound": "hbm",
         "kernel": dom,
@@ -679,7 +808,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32"}.get(head, "f16-store/f32"),
+        "dtype": {"fp64": "f64", "fp32": "f32"}.get(form_params(head)["precision"], "f16-store/f32"),
         "data": "synthetic",
         "config": {"workload": desc, "grid": [geom["nx"], geom["ny"], geom["nz"]], "form": head,
                    "step_path": r["step_path"], "nfluid": r["nfluid"]},

@@ -114,6 +114,19 @@ typedef struct lbfe_params {
  *                     (Eq. (11)): the populations are read once per step.
  *                     Not with moving walls or a solid mask, and only when
  *                     one z-plane of the lattice is below 2 GiB.
+ * LBFE_PATH_STATE     the moment-representation state of the paper's rate
+ *                     setting, every omega_k but omega_1 equal to 1 (Sec. II
+ *                     B, stated after Eq. (26)): between the steps of one
+ *                     lbfe_step call each node holds 16 post-collision
+ *                     numbers instead of 27 populations; per step the
+ *                     stencil chain, a collide pass and a moments pass each
+ *                     rebuild the populations from those numbers.  The
+ *                     first step of a call enters the state form from the
+ *                     populations, the last leaves it, so between calls the
+ *                     context holds populations as on the other paths.
+ *                     FP64 and FP32 only, resting walls, no solid mask, and
+ *                     a lattice z-plane below 2 GiB; lbfe_create rejects it
+ *                     with LBFE_E_INVAL otherwise (other rates included).
  * LBFE_ORDER_ROUND_ROBIN  workgroups in launch order (the hardware deals them
  *                     to the 8 XCDs in turn).
  * LBFE_ORDER_XCD      each XCD takes one contiguous range of tiles, so
@@ -121,6 +134,7 @@ typedef struct lbfe_params {
 #define LBFE_AUTO 0
 #define LBFE_PATH_TWO_PASS 1
 #define LBFE_PATH_FUSED 2
+#define LBFE_PATH_STATE 3
 #define LBFE_ORDER_ROUND_ROBIN 1
 #define LBFE_ORDER_XCD 2
 
@@ -194,8 +208,8 @@ int lbfe_init_density(lbfe_ctx *ctx, const double *rho0_dev, const double *u0_de
  * Each step runs as params.step_path says: a moments pass, the stencil
  * chain and a collide-stream pass (LBFE_PATH_TWO_PASS), or the stencil
  * chain and a collide-stream kernel that also forms the next step's density
- * and momentum (LBFE_PATH_FUSED, no moments pass); both give bitwise
- * identical states. */
+ * and momentum (LBFE_PATH_FUSED, no moments pass), or through the moment
+ * state (LBFE_PATH_STATE); all give bitwise identical states. */
 int lbfe_step(lbfe_ctx *ctx, int64_t nsteps);
 
 /* Timing variant of lbfe_step for benchmarks: the same launches, with HIP
@@ -204,8 +218,10 @@ int lbfe_step(lbfe_ctx *ctx, int64_t nsteps);
  * steps: 0 moments pass (with the wall density after it; on the fused path
  * only after the state was set from outside), 1 stencil chain (mu, force,
  * Q), 2 collide-stream (fused path: with the next step's moments), 3 wall
- * density after the step (fused path, walls only).  Synchronises after
- * every step (host array). */
+ * density after the step (fused path, walls only).  On the state path:
+ * 0 the moments passes (with the populations at the end and the wall
+ * density), 1 the chains, 2 the collide passes (the first from the
+ * populations), 3 zero.  Synchronises after every step (host array). */
 int lbfe_step_timed(lbfe_ctx *ctx, int64_t nsteps, double kernel_ms[4]);
 
 /* Number of steps taken since lbfe_init_density / lbfe_set_state. */

@@ -8,7 +8,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "liblbfe.so")
-SOURCES = ["lbfe_api.hip", "lbfe_kernels.hip", "lbfe_chain.hip", "lbfe_fused.hip", "lbfe_mask.hip",
+SOURCES = ["lbfe_api.hip", "lbfe_kernels.hip", "lbfe_chain.hip", "lbfe_fused.hip", "lbfe_moment.hip", "lbfe_mask.hip",
            "lbfe_adjoint.hip"]
 
 FLAGS = [

@@ -26,6 +26,7 @@ struct lbfe_ctx {
     int64_t step = 0;
     bool bound = false, initialised = false, adj_seeded = false;
     bool fused = false;   // fused collide-stream-moments step (LBFE_PATH_FUSED)
+    bool state = false;   // moment-representation state (LBFE_PATH_STATE)
     bool aux_ok = false;  // rho, j, mu0 hold the moments of f[cur]
     bool mask_set = false;  // a solid mask has been given (solid_mask = 1)
     bool lam_pending = false;  // lam[lcur] lacks its last term (see the adjoint kernels)
@@ -121,7 +122,15 @@ std::string validate(const lbfe_params &p) {
     if (p.solid_mask != 0 && p.solid_mask != 1) return "solid_mask must be 0 or 1";
     if (p.solid_mask && p.walls_z) return "solid_mask replaces walls_z (put the planes into the mask)";
     if (p.solid_mask && p.adjoint) return "the adjoint does not cover solid masks";
-    if (p.step_path < LBFE_AUTO || p.step_path > LBFE_PATH_FUSED) return "unknown step_path";
+    if (p.step_path < LBFE_AUTO || p.step_path > LBFE_PATH_STATE) return "unknown step_path";
+    if (p.step_path == LBFE_PATH_STATE) {  // the moment state: the paper's rates, storage and boundaries
+        if (p.precision != LBFE_FP64 && p.precision != LBFE_FP32) return "the moment-state path stores FP64 or FP32 only";
+        for (int k = 0; k < 11; ++k)
+            if (k != 1 && p.omega[k] != 1.0) return "the moment-state path needs every omega_k but omega_1 equal to 1";
+        if (moving) return "the moment-state path has resting walls only";
+        if (p.solid_mask) return "the moment-state path has no solid mask";
+        if (!state_plane_ok(p.precision, (size_t)p.nx * p.ny)) return "the moment-state path needs a z-plane below 2 GiB";
+    }
     if (p.tile_order < LBFE_AUTO || p.tile_order > LBFE_ORDER_XCD) return "unknown tile_order";
     if (p.chain_chunk < 0 || p.chain_chunk > 64) return "chain_chunk must be 0 (chosen per grid) or 1..64";
     return "";
@@ -245,6 +254,79 @@ Bufs with_aux(const lbfe_ctx *c, const void *aux) {
     b.F = a + L.F;
     b.Q = a + L.Q;
     return b;
+}
+
+// Steps through the moment state: the populations f[cur] enter the state
+// form with the first collision and leave it with the last streaming, so
+// between calls the context holds populations.  The state lattices are the
+// two population buffers in turn.  With kernel_ms, accumulates the launch
+// groups' times as lbfe_step_timed describes.
+int step_state(lbfe_ctx *c, int64_t nsteps, double *kernel_ms) {
+    if (nsteps == 0) return LBFE_OK;
+    const int prec = c->p.precision;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t *evp = nullptr;
+    if (kernel_ms) {
+        for (int k = 0; k < 3; ++k)
+            if (hipEventCreate(&ev[k]) != hipSuccess) {
+                for (int q = 0; q < k; ++q) (void)hipEventDestroy(ev[q]);
+                return fail(c, LBFE_E_DEVICE, "hipEventCreate failed");
+            }
+        evp = ev;
+    }
+    // events ev[0..n-1] of the last launch group: interval 0 to slot a, 1 to b
+    auto account = [&](int n, int a, int b) -> hipError_t {
+        if (!evp) return hipSuccess;
+        hipError_t e = hipEventSynchronize(ev[n - 1]);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+        kernel_ms[a] += ms;
+        if (e == hipSuccess && n == 3) {
+            e = hipEventElapsedTime(&ms, ev[1], ev[2]);
+            kernel_ms[b] += ms;
+        }
+        return e;
+    };
+    int rc = LBFE_OK;
+    int a = 1 - c->cur;  // the lattice holding the state
+    hipError_t e = launch_state_enter(c->stream, prec, c->kp, c->b, c->cur, !c->aux_ok, evp);
+    if (e == hipSuccess) e = account(3, 1, 2);
+    for (int64_t s = 0; s < nsteps && e == hipSuccess && rc == LBFE_OK; ++s) {
+        const bool last = s + 1 == nsteps;
+        // completes step s: the moments of the streamed state (populations too
+        // at the end)
+        e = launch_state_moments(c->stream, prec, c->kp, c->b, a, last, evp);
+        if (e == hipSuccess) e = account(2, 0, 0);
+        if (e != hipSuccess) break;
+        c->step++;
+        if (last) c->cur = 1 - a;
+        if ((s + 1) % c->p.check_every == 0 || last) {
+            int flag = 0;
+            if ((rc = read_flag(c, flag))) break;
+            if (flag) {
+                if (!last) {  // leave the state form
+                    e = launch_state_moments(c->stream, prec, c->kp, c->b, a, true, nullptr);
+                    c->cur = 1 - a;
+                    if (e != hipSuccess) break;
+                }
+                char buf[160];
+                std::snprintf(buf, sizeof buf, "diverged: NaN/Inf or density outside (0, 1/b) by step %lld",
+                              (long long)c->step);
+                rc = fail(c, LBFE_E_DIVERGED, buf);
+                break;
+            }
+        }
+        if (!last) {  // the collision of step s + 1
+            e = launch_state_collide(c->stream, prec, c->kp, c->b, a, evp);
+            if (e == hipSuccess) e = account(3, 1, 2);
+            a ^= 1;
+        }
+    }
+    for (int k = 0; k < 3; ++k)
+        if (ev[k]) (void)hipEventDestroy(ev[k]);
+    if (e != hipSuccess) return hip_fail(c, e, "step (moment state)");
+    c->aux_ok = true;
+    return rc;
 }
 
 }  // namespace
@@ -381,6 +463,7 @@ int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out) {
         return LBFE_E_INVAL;
     }
     c->fused = q.step_path == LBFE_PATH_FUSED;
+    c->state = q.step_path == LBFE_PATH_STATE;
     c->p = q;
     *out = c;
     return LBFE_OK;
@@ -473,6 +556,7 @@ int lbfe_step(lbfe_ctx *c, int64_t nsteps) {
     int r = need_init(c);
     if (r) return r;
     if (nsteps < 0) return fail(c, LBFE_E_INVAL, "nsteps < 0");
+    if (c->state) return step_state(c, nsteps, nullptr);
     for (int64_t s = 0; s < nsteps; ++s) {
         hipError_t e = launch_step(c->stream, c->p.precision, c->kp, c->b, c->cur, c->fused, !c->aux_ok, nullptr);
         if (e != hipSuccess) return hip_fail(c, e, "step");
@@ -504,6 +588,10 @@ int lbfe_step_timed(lbfe_ctx *c, int64_t nsteps, double kernel_ms[4]) {
             return fail(c, LBFE_E_DEVICE, "hipEventCreate failed");
         }
     for (int k = 0; k < 4; ++k) kernel_ms[k] = 0.0;
+    if (c->state) {
+        for (int k = 0; k < 5; ++k) (void)hipEventDestroy(ev[k]);
+        return step_state(c, nsteps, kernel_ms);
+    }
     int rc = LBFE_OK;
     for (int64_t s = 0; s < nsteps && rc == LBFE_OK; ++s) {
         hipError_t e = launch_step(c->stream, c->p.precision, c->kp, c->b, c->cur, c->fused, !c->aux_ok, ev);

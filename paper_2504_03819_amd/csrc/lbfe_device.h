@@ -272,9 +272,25 @@ template <class real> struct Rates {
     real w[11];
 };
 
+// The two deviatoric combinations of the normal second-order moments after
+// relaxation with omega_1 (Eq. (22)): A for k200 - k020, B for k200 - k002.
+template <class real> struct Dev2 {
+    real A, B;
+};
 template <class real>
-__device__ inline void collide(real (&k)[27], const Rates<real> &R, real Fx, real Fy, real Fz, real pm, real q200,
-                               real q020, real q002, real q220, real q202, real q022) {
+__device__ inline Dev2<real> dev2(const real (&k)[27], real w1, real q200, real q020, real q002) {
+    const real one = 1, half = 0.5;
+    const real k200 = k[K(2, 0, 0)], k020 = k[K(0, 2, 0)], k002 = k[K(0, 0, 2)];
+    return Dev2<real>{(one - w1) * (k200 - k020) + (one - half * w1) * (q200 - q020),
+                      (one - w1) * (k200 - k002) + (one - half * w1) * (q200 - q002)};
+}
+
+// The relaxation of Eqs. (21)-(26) with the normal second-order deviators D
+// given (dev2 of the same moments, for collide).
+template <class real>
+__device__ inline void collide_dev(real (&k)[27], const Rates<real> &R, const Dev2<real> &D, real Fx, real Fy,
+                                   real Fz, real pm, real q200, real q020, real q002, real q220, real q202,
+                                   real q022) {
     const real one = 1, half = 0.5, third = (real)(1.0 / 3.0), ninth = (real)(1.0 / 9.0);
     const real *w = R.w;
     // first order, Eq. (21)
@@ -287,13 +303,11 @@ __device__ inline void collide(real (&k)[27], const Rates<real> &R, real Fx, rea
     k[K(1, 0, 1)] *= (one - w[1]);
     {
         const real k200 = k[K(2, 0, 0)], k020 = k[K(0, 2, 0)], k002 = k[K(0, 0, 2)];
-        const real A = (one - w[1]) * (k200 - k020) + (one - half * w[1]) * (q200 - q020);
-        const real B = (one - w[1]) * (k200 - k002) + (one - half * w[1]) * (q200 - q002);
         const real S = (one - w[2]) * (k200 + k020 + k002) + (real)3 * w[2] * pm +
                        (one - half * w[2]) * (q200 + q020 + q002);
-        k[K(2, 0, 0)] = third * (S + A + B);
-        k[K(0, 2, 0)] = third * (S - (real)2 * A + B);
-        k[K(0, 0, 2)] = third * (S + A - (real)2 * B);
+        k[K(2, 0, 0)] = third * (S + D.A + D.B);
+        k[K(0, 2, 0)] = third * (S - (real)2 * D.A + D.B);
+        k[K(0, 0, 2)] = third * (S + D.A - (real)2 * D.B);
     }
     // third order, Eq. (23)
     {
@@ -337,11 +351,24 @@ __device__ inline void collide(real (&k)[27], const Rates<real> &R, real Fx, rea
     k[K(2, 2, 2)] = (one - w[10]) * k[K(2, 2, 2)] + w[10] * pm * ninth;
 }
 
-// ---------------------------------------------------------------------------
-// Collision of one fluid node: moments, u = (j + F/2)/rho, the local
-// omega_1 = 1/(rho nu/p_m + 1/2), CM transform, Eqs. (21)-(26), inverse
-// transform.  f: the arriving populations in, post-collision out.
-// ---------------------------------------------------------------------------
+template <class real>
+__device__ inline void collide(real (&k)[27], const Rates<real> &R, real Fx, real Fy, real Fz, real pm, real q200,
+                               real q020, real q002, real q220, real q202, real q022) {
+    collide_dev(k, R, dev2(k, R.w[1], q200, q020, q002), Fx, Fy, Fz, pm, q200, q020, q002, q220, q202, q022);
+}
+
+// Fourth-order corrections of Eq. (28) from the second-order ones (0 without corr4).
+template <class real> __device__ inline void q4_of(const KP &kp, real q200, real q020, real q002, real &q220,
+                                                   real &q202, real &q022) {
+    q220 = q202 = q022 = 0;
+    if (kp.corr4) {  // Eq. (28)
+        const real third = (real)(1.0 / 3.0);
+        q220 = (q200 + q020) * third;
+        q202 = (q200 + q002) * third;
+        q022 = (q020 + q002) * third;
+    }
+}
+
 // Node kinematics of Eqs. (11)-(12) and the rate after Eq. (26): u = (j +
 // F/2)/rho (as a product with 1/rho), p_m = (1 + mu)/3 and omega_1 =
 // 1/(rho nu/p_m + 1/2) in the form p_m/(rho nu + p_m/2).  Shared by the
@@ -363,6 +390,11 @@ __device__ inline Kin<real> kinematics(const KP &kp, double rd, real jx, real jy
     return q;
 }
 
+// ---------------------------------------------------------------------------
+// Collision of one fluid node: moments, u = (j + F/2)/rho, the local
+// omega_1 = 1/(rho nu/p_m + 1/2), CM transform, Eqs. (21)-(26), inverse
+// transform.  f: the arriving populations in, post-collision out.
+// ---------------------------------------------------------------------------
 template <class real>
 __device__ inline double collide_node(const KP &kp, real (&f)[27], double mu, real Fx, real Fy, real Fz, real q200,
                                       real q020, real q002) {
@@ -371,13 +403,8 @@ __device__ inline double collide_node(const KP &kp, real (&f)[27], double mu, re
     moments(f, rd, jx, jy, jz);
     const Kin<real> kin = kinematics(kp, rd, jx, jy, jz, Fx, Fy, Fz, mu);
     const real ux = kin.ux, uy = kin.uy, uz = kin.uz, pm = kin.pm;
-    real q220 = 0, q202 = 0, q022 = 0;
-    if (kp.corr4) {  // Eq. (28)
-        const real third = (real)(1.0 / 3.0);
-        q220 = (q200 + q020) * third;
-        q202 = (q200 + q002) * third;
-        q022 = (q020 + q002) * third;
-    }
+    real q220, q202, q022;
+    q4_of(kp, q200, q020, q002, q220, q202, q022);
     Rates<real> R;
 #pragma unroll
     for (int k = 0; k < 11; ++k) R.w[k] = (real)kp.om[k];
@@ -387,6 +414,85 @@ __device__ inline double collide_node(const KP &kp, real (&f)[27], double mu, re
     collide(f, R, Fx, Fy, Fz, pm, q200, q020, q002, q220, q202, q022);
     cm_inverse(f, ux, uy, uz);
     return rd;
+}
+
+// ---------------------------------------------------------------------------
+// Moment representation of the post-collision state.  With every rate but
+// omega_1 at 1 (the paper's setting, stated after Eq. (26)) the collision
+// leaves 16 numbers per node that fix all 27 post-collision central moments:
+//   m[0] k000 (the transform's zeroth moment, which the collision keeps),
+//   m[1..3] u, m[4..6] F, m[7] p_m, m[8..10] Q200, Q020, Q002,
+//   m[11..13] k*110, k*101, k*011 (relaxed with omega_1),
+//   m[14..15] the deviatoric pair A, B of dev2;
+// every other k* follows from Eqs. (21)-(26) at unit rates: k*100 = F_x/2,
+// the normal second-order moments from A, B and their trace 3 p_m + (Q200 +
+// Q020 + Q002)/2, k*120 = k*102 = F_x/6, k*111 = 0, the fourth-order triple
+// from p_m and the Q terms of Eq. (28), k*211 = 0, k*122 = F_x/18 and k*222 =
+// p_m/9.  state_populations rebuilds them with the collision's own code, so
+// its populations are those of collide_node (zero signs aside).
+// ---------------------------------------------------------------------------
+constexpr int kMState = 16;
+
+// The collision of collide_node, ending at the moment state: f, the
+// arriving populations, is consumed; m receives the node's state.  Returns
+// the density of the arriving populations.
+template <class real>
+__device__ inline double collide_to_state(const KP &kp, real (&f)[27], double mu, real Fx, real Fy, real Fz,
+                                          real q200, real q020, real q002, real (&m)[kMState]) {
+    double rd;
+    real jx, jy, jz;
+    moments(f, rd, jx, jy, jz);
+    const Kin<real> kin = kinematics(kp, rd, jx, jy, jz, Fx, Fy, Fz, mu);
+    real q220, q202, q022;
+    q4_of(kp, q200, q020, q002, q220, q202, q022);
+    Rates<real> R;
+#pragma unroll
+    for (int k = 0; k < 11; ++k) R.w[k] = (real)kp.om[k];
+    R.w[1] = kin.om1;
+    cm_forward(f, kin.ux, kin.uy, kin.uz);
+    const Dev2<real> D = dev2(f, kin.om1, q200, q020, q002);
+    const real one = 1;
+    m[0] = f[K(0, 0, 0)];
+    m[1] = kin.ux;
+    m[2] = kin.uy;
+    m[3] = kin.uz;
+    m[4] = Fx;
+    m[5] = Fy;
+    m[6] = Fz;
+    m[7] = kin.pm;
+    m[8] = q200;
+    m[9] = q020;
+    m[10] = q002;
+    m[11] = (one - kin.om1) * f[K(1, 1, 0)];
+    m[12] = (one - kin.om1) * f[K(1, 0, 1)];
+    m[13] = (one - kin.om1) * f[K(0, 1, 1)];
+    m[14] = D.A;
+    m[15] = D.B;
+    return rd;
+}
+
+// The 27 post-collision populations of a node from its moment state: the
+// relaxation of collide_dev, with the node's rates, applied to central
+// moments that are zero but for k000 and the omega_1-relaxed ones (those
+// with omega_1 taken as 0, the deviators given).  At unit rates every other
+// pre-collision moment enters multiplied by 0, so the moments and their
+// roundings are those of the collision that made the state.
+template <class real> __device__ inline void state_populations(const KP &kp, const real (&m)[kMState], real (&f)[27]) {
+    const real Fx = m[4], Fy = m[5], Fz = m[6], pm = m[7], q200 = m[8], q020 = m[9], q002 = m[10];
+    real q220, q202, q022;
+    q4_of(kp, q200, q020, q002, q220, q202, q022);
+#pragma unroll
+    for (int i = 0; i < 27; ++i) f[i] = 0;
+    f[K(0, 0, 0)] = m[0];
+    f[K(1, 1, 0)] = m[11];
+    f[K(1, 0, 1)] = m[12];
+    f[K(0, 1, 1)] = m[13];
+    Rates<real> R;
+#pragma unroll
+    for (int k = 0; k < 11; ++k) R.w[k] = (real)kp.om[k];
+    R.w[1] = 0;
+    collide_dev(f, R, Dev2<real>{m[14], m[15]}, Fx, Fy, Fz, pm, q200, q020, q002, q220, q202, q022);
+    cm_inverse(f, m[1], m[2], m[3]);
 }
 
 // Populations of the generalized equilibrium of Eq. (20) at (rho, p_m) and

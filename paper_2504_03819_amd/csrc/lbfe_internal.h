@@ -71,6 +71,30 @@ hipError_t launch_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int
 // fused_plane_ok: one z-plane of the lattice fits its 32-bit plane offsets
 hipError_t launch_fused(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur);
 bool fused_plane_ok(int prec, size_t plane);
+// Moment-representation state (lbfe_moment.hip), for unit rates but omega_1:
+// passes over a state lattice `sin` (16 values per node): kStateMoments forms
+// rho, j, mu0 of the streamed state, kStatePops also writes its populations
+// to the lattice `out`, kStateCollide collides the streamed state with the
+// current mu, F, Q and writes the new state to `out`; launch_state_first
+// collides the populations `fin` into the state lattice `sout`.  FP64 and
+// FP32 only (hipErrorInvalidValue otherwise).  state_plane_ok: one z-plane of
+// either lattice fits its 32-bit plane offsets.
+enum StateMode { kStateMoments = 0, kStatePops = 1, kStateCollide = 2 };
+hipError_t launch_state_pass(hipStream_t s, int prec, int mode, const KP &kp, const Bufs &b, const void *sin,
+                             void *out);
+hipError_t launch_state_first(hipStream_t s, int prec, const KP &kp, const Bufs &b, const void *fin, void *sout);
+bool state_plane_ok(int prec, size_t plane);
+// The state form's launch groups (lbfe_kernels.hip); ev, when non-null,
+// receives events at the start, after the chain (enter, collide) and at the
+// end.  enter: [moments of f[cur] if refresh], chain, f[cur] collided into
+// the state lattice f[1 - cur].  moments: rho, j, mu0 (and with `pops` the
+// populations, into f[1 - a]) of the state f[a], wall densities.  collide:
+// chain, then the state f[a] stepped into f[1 - a].
+hipError_t launch_state_enter(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, bool refresh,
+                              hipEvent_t *ev);
+hipError_t launch_state_moments(hipStream_t s, int prec, const KP &kp, const Bufs &b, int a, bool pops,
+                                hipEvent_t *ev);
+hipError_t launch_state_collide(hipStream_t s, int prec, const KP &kp, const Bufs &b, int a, hipEvent_t *ev);
 // mu, F and Q of the current rho, j (lbfe_chain.hip); chain_chunk_for: the
 // planes per workgroup, kp.chain_cz if set, else chosen for the grid
 hipError_t launch_chain(hipStream_t s, int prec, const KP &kp, const Bufs &b);

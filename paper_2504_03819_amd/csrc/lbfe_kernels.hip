@@ -449,6 +449,47 @@ hipError_t launch_step(hipStream_t s, int prec, const KP &kp, const Bufs &b, int
                     [&](auto pc) { return step_impl<decltype(pc)::value>(s, kp, b, cur, fused, refresh, ev5); });
 }
 
+// Moment-state launch groups (the kernels are in lbfe_moment.hip)
+hipError_t launch_state_enter(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, bool refresh,
+                              hipEvent_t *ev) {
+    const unsigned gf = nblocks(kp.nfluid), gw = nblocks(2 * (size_t)kp.plane);
+    if (ev) (void)hipEventRecord(ev[0], s);
+    if (refresh) {
+        hipError_t e = dispatch(prec, [&](auto pc) {
+            k_moments<decltype(pc)::value><<<gf, kBlock, 0, s>>>(kp, b.f[cur], b.rho, b.j, b.mu0, b.flag);
+            return hipGetLastError();
+        });
+        if (e != hipSuccess) return e;
+        if (kp.walls) k_wall_rho<<<gw, kBlock, 0, s>>>(kp, b.rho);
+    }
+    hipError_t e = launch_chain(s, prec, kp, b);
+    if (e != hipSuccess) return e;
+    if (ev) (void)hipEventRecord(ev[1], s);
+    e = launch_state_first(s, prec, kp, b, b.f[cur], b.f[1 - cur]);
+    if (ev) (void)hipEventRecord(ev[2], s);
+    return e;
+}
+
+hipError_t launch_state_moments(hipStream_t s, int prec, const KP &kp, const Bufs &b, int a, bool pops,
+                                hipEvent_t *ev) {
+    if (ev) (void)hipEventRecord(ev[0], s);
+    hipError_t e = launch_state_pass(s, prec, pops ? kStatePops : kStateMoments, kp, b, b.f[a], pops ? b.f[1 - a] : nullptr);
+    if (e != hipSuccess) return e;
+    if (kp.walls) k_wall_rho<<<nblocks(2 * (size_t)kp.plane), kBlock, 0, s>>>(kp, b.rho);
+    if (ev) (void)hipEventRecord(ev[1], s);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_collide(hipStream_t s, int prec, const KP &kp, const Bufs &b, int a, hipEvent_t *ev) {
+    if (ev) (void)hipEventRecord(ev[0], s);
+    hipError_t e = launch_chain(s, prec, kp, b);
+    if (e != hipSuccess) return e;
+    if (ev) (void)hipEventRecord(ev[1], s);
+    e = launch_state_pass(s, prec, kStateCollide, kp, b, b.f[a], b.f[1 - a]);
+    if (ev) (void)hipEventRecord(ev[2], s);
+    return e;
+}
+
 hipError_t launch_export(hipStream_t s, int prec, const KP &kp, const Bufs &b, int which, double *out) {
     return dispatch(prec, [&](auto pc) {
         constexpr int P = decltype(pc)::value;

@@ -13,7 +13,7 @@ LIB_PATH = os.environ.get("LBFE_LIB") or os.path.join(os.path.dirname(os.path.ab
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_DIVERGED, E_STATE = 0, -1, -2, -3, -4, -5
 FP64, FP32, FP16_DEV, FP16_DEV_F0FP32 = 0, 1, 2, 3
 WET_NEUTRAL, WET_PHI, WET_DELTA = 0, 1, 2
-AUTO, PATH_TWO_PASS, PATH_FUSED = 0, 1, 2
+AUTO, PATH_TWO_PASS, PATH_FUSED, PATH_STATE = 0, 1, 2, 3
 ORDER_ROUND_ROBIN, ORDER_XCD = 1, 2
 FIELD_RHO, FIELD_U, FIELD_MU, FIELD_F, FIELD_Q, FIELD_PM = 0, 1, 2, 3, 4, 5
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "fp16dev": FP16_DEV, "fp16dev_f0fp32": FP16_DEV_F0FP32}

@@ -71,6 +71,13 @@ def test_coexistence_matches_oracle_maxwell():
     dict(wall_u=(0.1, 0.0, 0.0, 0.0)), dict(walls_z=1, wall_u=(0.0, 0.0, 0.31, 0.0)),
     dict(walls_z=1, adjoint=1, wall_u=(0.1, 0.0, 0.1, 0.0)), dict(walls_z=1, wall_u=(float("nan"), 0.0, 0.0, 0.0)),
     dict(solid_mask=2), dict(solid_mask=1, walls_z=1), dict(solid_mask=1, adjoint=1),
+    # the moment-state path: the paper's unit rates, FP64/FP32, resting walls, no mask
+    dict(step_path=4), dict(step_path=lbfe.PATH_STATE, precision=lbfe.FP16_DEV),
+    dict(step_path=lbfe.PATH_STATE, precision=lbfe.FP16_DEV_F0FP32),
+    dict(step_path=lbfe.PATH_STATE, omega=(1.0, 1.0, 1.0, 0.5) + (1.0,) * 7),
+    dict(step_path=lbfe.PATH_STATE, omega=(0.9,) + (1.0,) * 10),
+    dict(step_path=lbfe.PATH_STATE, walls_z=1, wall_u=(0.0, 0.0, 0.05, 0.0)),
+    dict(step_path=lbfe.PATH_STATE, solid_mask=1),
 ])
 def test_invalid_parameters_rejected_before_device(override):
     p = lbfe.default_params()
@@ -103,6 +110,17 @@ def test_omega_range_checked_but_omega1_ignored():
     assert lbfe.lib().lbfe_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == lbfe.OK
     p.omega[4] = 2.5
     assert lbfe.lib().lbfe_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == lbfe.E_INVAL
+
+
+def test_state_path_accepted_for_the_papers_rates():
+    """Every rate but omega_1 at 1 (omega_1 itself comes from nu), FP64 or
+    FP32, periodic or resting walls, with or without corr4."""
+    for prec in (lbfe.FP64, lbfe.FP32):
+        for extra in (dict(), dict(walls_z=1, wet_mode=1, wet_value=1.3), dict(corr4=0)):
+            p = lbfe.default_params(precision=prec, step_path=lbfe.PATH_STATE, **extra)
+            p.omega[1] = 0.4
+            n = ctypes.c_size_t()
+            assert lbfe.lib().lbfe_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == lbfe.OK, (prec, extra)
 
 
 def test_workspace_size_accounts_for_forms_and_adjoint():
