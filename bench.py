@@ -699,6 +699,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calib", action="store_true", help="run a 1 GiB device copy first (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    ap.add_argument("--counters-out", default=COUNTERS,
+                    help="where --summarize-counters writes (the bench line reads profiles/collide_counters.json)")
     ap.add_argument("--adjoint-only", action="store_true", help="time only the adjoint leg, print its JSON")
     ap.add_argument("--adjoint-steps", type=int, default=20)
     ap.add_argument("--collision-adjoint", nargs=3, type=int, metavar=("FORWARD", "ADJOINT", "SNAPSHOTS"),
@@ -716,7 +718,7 @@ def main():
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, form=args.forms.split(",")[0], workload_name=args.workload,
-                           out_path=COUNTERS)
+                           out_path=args.counters_out)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         sys.stderr.write("bench.py: runs on one GPU only; a multi-GPU (z-slab) decomposition "
