@@ -510,8 +510,9 @@ def wetting_angles(lbfe, torch, steps=40000, every=10000, form="fp64", cases=Non
     return out
 
 
-def time_collision_adjoint(lbfe, torch, forward=5000, adjoint=500, snapshots=8):
-    """512^3 head-on collision in FP32: `forward` steps, then the adjoint of
+def time_collision_adjoint(lbfe, torch, forward=5000, adjoint=500, snapshots=8, form="fp32"):
+    """512^3 head-on collision in a storage form (FP32 by default; the
+    adjoint runs in the form's compute precision): `forward` steps, then the adjoint of
     the last `adjoint` steps from the stored state f(T - adjoint) with the
     binomial checkpoint schedule (`snapshots` states held), loss
     L = sum (rho_T - rho_0)^2.  Reports forward and backward times, the
@@ -523,7 +524,7 @@ def time_collision_adjoint(lbfe, torch, forward=5000, adjoint=500, snapshots=8):
     from paper_2504_03819_amd import inputs
     rho0, u0 = inputs.head_on_collision(rl, rv)
     torch.cuda.reset_peak_memory_stats()
-    sim = lbfe.Simulation(device="cuda:0", nx=n, ny=n, nz=n, T=T, precision="fp32", adjoint=1, check_every=500)
+    sim = lbfe.Simulation(device="cuda:0", nx=n, ny=n, nz=n, T=T, precision=form, adjoint=1, check_every=500)
     r0 = torch.tensor(rho0, device="cuda:0")
     sim.init_density(r0, torch.tensor(u0))
     del rho0, u0
@@ -552,7 +553,7 @@ def time_collision_adjoint(lbfe, torch, forward=5000, adjoint=500, snapshots=8):
     adj_ms = (bwd_ms - stats["recompute_steps"] * fwd_ms) / adjoint
     g = sim.adjoint_grads()
     nodes = n ** 3
-    out = {"workload": "head-on collision 512^3 FP32, two r=64 droplets 160 apart at +-0.04, T=0.85Tc",
+    out = {"workload": f"head-on collision 512^3 {form}, two r=64 droplets 160 apart at +-0.04, T=0.85Tc",
            "forward_steps": forward, "adjoint_steps": adjoint, "snapshots": snapshots,
            "recompute_steps": stats["recompute_steps"], "ms_per_forward_step": fwd_ms,
            "mlups_forward": nodes / (fwd_ms / 1e3) / 1e6, "backward_s": bwd_ms / 1e3,
@@ -703,6 +704,7 @@ def main():
                     help="where --summarize-counters writes (the bench line reads profiles/collide_counters.json)")
     ap.add_argument("--adjoint-only", action="store_true", help="time only the adjoint leg, print its JSON")
     ap.add_argument("--adjoint-steps", type=int, default=20)
+    ap.add_argument("--adjoint-form", default="fp32", help="storage form of --collision-adjoint")
     ap.add_argument("--collision-adjoint", nargs=3, type=int, metavar=("FORWARD", "ADJOINT", "SNAPSHOTS"),
                     help="time the 512^3 collision with a binomial-checkpointed adjoint of its last steps")
     ap.add_argument("--wetting-adjoint", nargs=3, type=int, metavar=("STEPS", "CHECKPOINT_EVERY", "NEUTRAL"),
@@ -747,7 +749,8 @@ def main():
               flush=True)
         return
     if args.collision_adjoint:
-        print(json.dumps(time_collision_adjoint(lbfe, torch, *args.collision_adjoint)), flush=True)
+        print(json.dumps(time_collision_adjoint(lbfe, torch, *args.collision_adjoint, form=args.adjoint_form)),
+              flush=True)
         return
     if args.adjoint_only:
         print(json.dumps(time_adjoint(lbfe, torch, steps=args.adjoint_steps)), flush=True)
