@@ -3,7 +3,10 @@ CPU).  Documents a property of the method as read here: with every
 higher-order rate at 1, a wall bounding the 0.7 T_c vapour has an unstable
 mode (tangential velocity alternating in x along the first fluid layer);
 omega_3 = 0.5 removes it; the same vapour without walls is neutrally
-stable."""
+stable.  With moving walls (the momentum-corrected bounce-back of the
+moving-wall test, Sec. III B) the same holds around the vapour moving with
+the walls and around the sheared vapour between walls moving in opposite
+directions: the wall mode at omega_3 = 1, neutral at omega_3 = 1/2."""
 import numpy as np
 import torch
 
@@ -27,7 +30,7 @@ def spectral_radius(walls, omega3, tr=0.7, nu=0.15):
         f = f0.reshape(-1).index_put((idx,), v)
         return lbm.step(f.reshape(f0.shape), p).reshape(-1)[idx]
 
-    J = torch.autograd.functional.jacobian(F, f0.reshape(-1)[idx])
+    J = torch.autograd.functional.jacobian(F, f0.reshape(-1)[idx], vectorize=True)
     return float(np.abs(np.linalg.eigvals(J.numpy())).max())
 
 
@@ -37,3 +40,36 @@ def test_wall_vapour_mode():
     assert abs(spectral_radius(False, 1.0) - 1.0) < 1e-9
     assert abs(spectral_radius(True, 0.5, nu=0.03) - 1.0) < 1e-3
     assert abs(spectral_radius(True, 1.0, tr=0.8) - 1.0) < 1e-9
+
+
+def moving_wall_radius(omega3, U, Ut, base_steps, nx=2, nz=6, tr=0.7, nu=0.15):
+    """Spectral radius of the linearised step around the 0.7 T_c vapour
+    between walls moving at U (bottom) and Ut (top), started from the linear
+    Couette profile and stepped base_steps times towards its steady state
+    (with U = Ut the vapour moving with the walls is a fixed point)."""
+    om = [1.0] * 11
+    om[3] = omega3
+    p = lbm.Params(nx, 1, nz, walls_z=True, T=eos.temperature(tr), omega=om, nu=nu, wall_u=(U, 0.0, Ut, 0.0))
+    rl, rv = p.coexistence()
+    u = torch.zeros((3, nz, 1, nx), dtype=torch.float64)
+    z = torch.arange(nz, dtype=torch.float64)
+    u[0] = (U + (Ut - U) * (z - 0.5) / (nz - 2)).reshape(nz, 1, 1)
+    f = lbm.init(torch.full((nz, 1, nx), rv, dtype=torch.float64), p, u)
+    for _ in range(base_steps):
+        f = lbm.step(f, p)
+    keep = torch.ones_like(f, dtype=torch.bool)
+    keep[:, 0] = False
+    keep[:, -1] = False
+    idx = keep.reshape(-1).nonzero().squeeze(1)
+
+    def F(v):
+        return lbm.step(f.reshape(-1).index_put((idx,), v).reshape(f.shape), p).reshape(-1)[idx]
+
+    J = torch.autograd.functional.jacobian(F, f.reshape(-1)[idx], vectorize=True)
+    return float(np.abs(np.linalg.eigvals(J.numpy())).max())
+
+
+def test_moving_wall_vapour_modes():
+    assert moving_wall_radius(1.0, 0.1, 0.1, 0) > 1.15
+    assert abs(moving_wall_radius(0.5, 0.1, 0.1, 0) - 1.0) < 1e-9
+    assert abs(moving_wall_radius(0.5, 0.1, -0.1, 300) - 1.0) < 1e-9
