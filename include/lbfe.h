@@ -112,8 +112,10 @@ typedef struct lbfe_params {
  * LBFE_PATH_FUSED     the stencil chain, then one kernel that collides,
  *                     streams and forms the next step's density and momentum
  *                     (Eq. (11)): the populations are read once per step.
- *                     Not with moving walls or a solid mask, and only when
- *                     one z-plane of the lattice is below 2 GiB.
+ *                     Not with a solid mask, and only when one z-plane of
+ *                     the lattice is below 2 GiB (moving walls: the wall
+ *                     term and the moments of the two wall-adjacent planes
+ *                     are applied by a small pass after the kernel).
  * LBFE_PATH_STATE     the moment-representation state of the paper's rate
  *                     setting, every omega_k but omega_1 equal to 1 (Sec. II
  *                     B, stated after Eq. (26)): between the steps of one

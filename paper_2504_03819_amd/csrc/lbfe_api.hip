@@ -145,9 +145,9 @@ bool moving_walls(const lbfe_params &p) {
     return p.wall_u[0] != 0.0 || p.wall_u[1] != 0.0 || p.wall_u[2] != 0.0 || p.wall_u[3] != 0.0;
 }
 
-// the fused step path is possible: resting walls, no mask, 32-bit plane offsets
+// the fused step path is possible: no mask, 32-bit plane offsets
 bool fused_possible(const lbfe_params &p) {
-    return !moving_walls(p) && !p.solid_mask && fused_plane_ok(p.precision, (size_t)p.nx * p.ny);
+    return !p.solid_mask && fused_plane_ok(p.precision, (size_t)p.nx * p.ny);
 }
 
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
@@ -446,8 +446,8 @@ int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out) {
     k.chain_cz = q.chain_chunk;
     q.chain_chunk = k.chain_cz = chain_chunk_for(k);
     // Step path: the fused collide-stream-moments kernel reads the
-    // populations once per step; it has resting walls, no solid mask, and
-    // addresses one z-plane of the lattice with 32-bit offsets.  Measured on
+    // populations once per step; it has no solid mask, and addresses one
+    // z-plane of the lattice with 32-bit offsets.  Measured on
     // gfx950 it is faster in FP64 on large grids (256^3: 2.44 against
     // 2.76 ms per step; 512^3: 19.0 against 22.1 ms) and slower in the FP32
     // and FP16 forms, whose collide-stream pass alone runs closer to the
@@ -457,8 +457,8 @@ int lbfe_create(const lbfe_params *p, void *hip_stream, lbfe_ctx **out) {
     if (q.step_path == LBFE_AUTO)
         q.step_path = fused_ok && q.precision == LBFE_FP64 && k.N >= (1u << 24) ? LBFE_PATH_FUSED : LBFE_PATH_TWO_PASS;
     if (q.step_path == LBFE_PATH_FUSED && !fused_ok) {
-        std::fprintf(stderr, "lbfe_create: the fused step path needs resting walls, no solid mask and "
-                             "a lattice z-plane below 2 GiB\n");
+        std::fprintf(stderr, "lbfe_create: the fused step path needs no solid mask and a lattice z-plane below "
+                             "2 GiB\n");
         delete c;
         return LBFE_E_INVAL;
     }

@@ -197,6 +197,64 @@ template <int P> __global__ __launch_bounds__(kBlock) void k_wall_move(KP kp, vo
     }
 }
 
+// Moving walls on the fused path.  k_fused reflects at the walls without the
+// wall-velocity term and overwrites rho of the first and last fluid planes
+// with rho(t+1).  k_wall_keep first copies rho(t) of those planes into the
+// density slots of the adjacent solid planes, which nothing reads before
+// k_wall_rho refills them; k_wall_move_fused then applies the term exactly
+// as k_wall_move does and forms rho, j, mu0 of the corrected nodes again
+// from their stored populations, as k_moments would (so the fused path with
+// moving walls gives the two-pass path's bits).
+__global__ __launch_bounds__(kBlock) void k_wall_keep(KP kp, double *rho) {
+    const unsigned p = blockIdx.x * kBlock + threadIdx.x;
+    if (p >= kp.plane) return;
+    rho[p] = rho[kp.plane + p];
+    rho[(size_t)(kp.nz - 1) * kp.plane + p] = rho[(size_t)(kp.nz - 2) * kp.plane + p];
+}
+
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_wall_move_fused(KP kp, void *fq, double *rho, const double *mu, void *jq,
+                                                          double *mu0, int *flag) {
+    using real = real_t<P>;
+    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= 2 * kp.plane) return;
+    const int side = idx >= kp.plane;
+    const unsigned p = idx - (side ? kp.plane : 0u);
+    const int z = side ? kp.nz - 2 : 1;
+    if (side && z == 1) return;  // one fluid plane: both walls handled by side 0
+    const unsigned y = p / (unsigned)kp.nx, x = p - y * (unsigned)kp.nx;
+    const size_t n = (size_t)z * kp.plane + p;
+    const unsigned row = (unsigned)z * (unsigned)kp.ny + y;
+    const Pops<P> f(fq, kp);
+    const double rt = rho[(size_t)(side ? kp.nz - 1 : 0) * kp.plane + p];  // rho(t), kept by k_wall_keep
+    const real r = (real)rt, pm = (real)((1.0 + mu[n]) * (1.0 / 3.0));
+    real fe[27];
+    for (int w = 0; w < 2; ++w) {  // bottom, top
+        const bool hit = w == 0 ? z == 1 : z == kp.nz - 2;
+        if (!hit) continue;
+        wall_equilibrium(r, pm, (real)kp.wall_u[2 * w], (real)kp.wall_u[2 * w + 1], fe);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const int cz = czi(i);
+            if ((w == 0 && cz < 0) || (w == 1 && cz > 0))
+                f.st(26 - i, row, x, f.ld(26 - i, row, x) - (fe[i] - fe[26 - i]));
+        }
+    }
+    real v[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) v[i] = f.ld(i, row, x);
+    double rn;
+    real jx, jy, jz;
+    moments(v, rn, jx, jy, jz);
+    rho[n] = rn;
+    mu0[n] = mu_bulk(kp, rn);
+    real *j = (real *)jq;
+    j[n] = jx;
+    j[kp.N + n] = jy;
+    j[2 * (size_t)kp.N + n] = jz;
+    if (!(rn > 0.0 && kp.b * rn < 1.0)) *flag = 1;
+}
+
 // Initial populations: inverse CM transform of the Eq. (20) equilibrium.
 template <int P>
 __global__ __launch_bounds__(kBlock) void k_init(KP kp, const double *rho0, const double *u0, const double *mu,
@@ -388,8 +446,10 @@ hipError_t step_impl(hipStream_t s, const KP &kp, const Bufs &b, int cur, bool f
     if (e != hipSuccess) return e;
     mark(2);
     if (fused) {
+        if (kp.moving) k_wall_keep<<<nblocks(kp.plane), kBlock, 0, s>>>(kp, b.rho);
         e = launch_fused(s, P, kp, b, cur);
         if (e != hipSuccess) return e;
+        if (kp.moving) k_wall_move_fused<P><<<gw, kBlock, 0, s>>>(kp, b.f[1 - cur], b.rho, b.mu, b.j, b.mu0, b.flag);
     } else {
         k_collide<P><<<nblocks(kp.nfluid), kBlock, 0, s>>>(kp, b.f[cur], b.f[1 - cur], b.mu, b.F, b.Q);
         if (kp.moving) k_wall_move<P><<<gw, kBlock, 0, s>>>(kp, b.f[1 - cur], b.rho, b.mu);

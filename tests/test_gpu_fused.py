@@ -3,7 +3,8 @@
 the same fixed order, so populations, density, momentum and the derived
 fields must agree bit for bit after every step, for every storage form, on
 grids smaller than a tile, ragged grids spanning several tiles and chunks,
-and walled boxes."""
+walled boxes, and walled boxes with moving walls (the wall term applied after
+the fused kernel)."""
 import numpy as np
 import pytest
 import torch
@@ -21,6 +22,9 @@ CASES = [
     ("ragged 40x37x70", (40, 37, 70), False, {}),
     ("walls phi 1.4 34x21x45", (34, 21, 45), True, dict(wet_mode=1, wet_value=1.4)),
     ("walls drho 0.9 3-plane", (3, 20, 33), True, dict(wet_mode=2, wet_value=0.9)),
+    ("moving walls phi 1.3 30x22x41", (30, 22, 41), True,
+     dict(wet_mode=1, wet_value=1.3, wall_u=(0.08, -0.03, -0.05, 0.02))),
+    ("moving walls 3-plane", (3, 17, 35), True, dict(wall_u=(0.1, 0.0, -0.1, 0.05))),
 ]
 
 
