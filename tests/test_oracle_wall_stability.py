@@ -10,7 +10,7 @@ directions: the wall mode at omega_3 = 1, neutral at omega_3 = 1/2."""
 import numpy as np
 import torch
 
-from oracle import eos, lbm
+from oracle import eos, lattice, lbm
 
 
 def spectral_radius(walls, omega3, tr=0.7, nu=0.15):
@@ -73,3 +73,30 @@ def test_moving_wall_vapour_modes():
     assert moving_wall_radius(1.0, 0.1, 0.1, 0) > 1.15
     assert abs(moving_wall_radius(0.5, 0.1, 0.1, 0) - 1.0) < 1e-9
     assert abs(moving_wall_radius(0.5, 0.1, -0.1, 300) - 1.0) < 1e-9
+
+
+def test_nyquist_mode_is_undamped():
+    """The uniform 0.7 T_c liquid moving at u_x = 0.1 (periodic, no walls):
+    the step has an eigenvalue -1 whose mode alternates density and x-momentum
+    from node to node (the wavenumber pi in x), on which the central-difference
+    gradient of the force vanishes; nothing damps it."""
+    om = [1.0] * 11
+    om[3] = 0.5
+    nx = 2
+    p = lbm.Params(nx, 1, 1, walls_z=False, T=eos.temperature(0.7), omega=om, nu=0.15)
+    rl, rv = p.coexistence()
+    u = torch.zeros((3, 1, 1, nx), dtype=torch.float64)
+    u[0] = 0.1
+    f = lbm.init(torch.full((1, 1, nx), rl, dtype=torch.float64), p, u)
+    J = torch.autograd.functional.jacobian(lambda v: lbm.step(v.reshape(f.shape), p).reshape(-1), f.reshape(-1),
+                                           vectorize=True).numpy()
+    ev, V = np.linalg.eig(J)
+    assert np.abs(ev).max() < 1 + 1e-12
+    k = int(np.argmin(np.abs(ev + 1)))
+    assert abs(ev[k] + 1) < 1e-12
+    v = np.real(V[:, k]).reshape(f.shape)
+    drho = v[:, 0, 0, :].sum(0)
+    cx = np.array([lattice.C_T[i][0] for i in range(27)], dtype=float)
+    djx = (cx[:, None] * v[:, 0, 0, :]).sum(0)
+    assert abs(drho[0] + drho[1]) < 1e-12 * abs(drho[0]) and abs(drho[0]) > 1e-3
+    assert abs(djx[0] + djx[1]) < 1e-12 * abs(djx[0]) and abs(djx[0]) > 1e-3
