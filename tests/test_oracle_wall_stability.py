@@ -6,7 +6,10 @@ omega_3 = 0.5 removes it; the same vapour without walls is neutrally
 stable.  With moving walls (the momentum-corrected bounce-back of the
 moving-wall test, Sec. III B) the same holds around the vapour moving with
 the walls and around the sheared vapour between walls moving in opposite
-directions: the wall mode at omega_3 = 1, neutral at omega_3 = 1/2."""
+directions: the wall mode at omega_3 = 1, neutral at omega_3 = 1/2.  In the
+uniform phases the step leaves the Nyquist mode in x (alternating density
+and momentum, on which the central-difference force vanishes) undamped:
+eigenvalue -1."""
 import numpy as np
 import torch
 
