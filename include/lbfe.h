@@ -93,7 +93,7 @@ typedef struct lbfe_params {
                             (z = 0) and top (z = nz-1) walls, moving-wall
                             test of Sec. III B: momentum-corrected halfway
                             bounce-back; |u| <= 0.3; nonzero needs
-                            walls_z = 1 and adjoint = 0; 0 = resting walls */
+                            walls_z = 1; 0 = resting walls */
     int32_t solid_mask;  /* 1: the solid nodes come from a voxel mask given
                             by lbfe_set_solid (needs walls_z = 0, adjoint =
                             0, resting walls); 0: none or the wall planes */

@@ -375,6 +375,27 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
             }
         }
     }
+    // moving walls: a reflected population carries -[f^eq_i - f^eq_opp(i)](rho,
+    // p_m, u_w) (k_wall_move), which is linear in (rho, p_m) at a given u_w;
+    // its adjoint adds to the node's rho_bar and p_m_bar
+    double wrb = 0.0, wpb = 0.0;
+    if (kp.moving && (wall_lo || wall_hi)) {
+        for (int w = 0; w < 2; ++w) {
+            if (!(w == 0 ? wall_lo : wall_hi)) continue;
+            real ea[27], eb[27];
+            const real uwx = (real)kp.wall_u[2 * w], uwy = (real)kp.wall_u[2 * w + 1];
+            wall_equilibrium((real)1, (real)0, uwx, uwy, ea);
+            wall_equilibrium((real)0, (real)1, uwx, uwy, eb);
+#pragma unroll
+            for (int i = 0; i < 27; ++i) {
+                const int cz = czi(i);
+                if ((w == 0 && cz < 0) || (w == 1 && cz > 0)) {
+                    wrb -= (double)l[i] * (double)(ea[i] - ea[26 - i]);
+                    wpb -= (double)l[i] * (double)(eb[i] - eb[26 - i]);
+                }
+            }
+        }
+    }
     cm_inverse_T(l, ux, uy, uz);  // l = lambda_hat (adjoint of k*)
     real ubx, uby, ubz;
     shift_dot(l, ks, ubx, uby, ubz);  // lambda_hat . S k*
@@ -399,8 +420,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     // omega_1 = 1 / (rho nu / p_m + 1/2)
     const double o = (double)om1, dpm = (double)pm, rr = rd;
     const double om1b = (double)sb.om1;
-    const double rhob = -om1b * o * o * kp.nu / dpm;
-    const double pmb = (double)sb.pm + om1b * o * o * rr * kp.nu / (dpm * dpm);
+    const double rhob = -om1b * o * o * kp.nu / dpm + wrb;
+    const double pmb = (double)sb.pm + om1b * o * o * rr * kp.nu / (dpm * dpm) + wpb;
     const double nub = -om1b * o * o * rr / dpm;
     const size_t N = kp.N;
     double *A = (double *)b.abuf;

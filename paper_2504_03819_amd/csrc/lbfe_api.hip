@@ -118,7 +118,6 @@ std::string validate(const lbfe_params &p) {
         moving = moving || p.wall_u[k] != 0.0;
     }
     if (moving && !p.walls_z) return "moving walls need walls_z = 1";
-    if (moving && p.adjoint) return "the adjoint does not cover moving walls";
     if (p.solid_mask != 0 && p.solid_mask != 1) return "solid_mask must be 0 or 1";
     if (p.solid_mask && p.walls_z) return "solid_mask replaces walls_z (put the planes into the mask)";
     if (p.solid_mask && p.adjoint) return "the adjoint does not cover solid masks";

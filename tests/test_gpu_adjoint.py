@@ -39,6 +39,8 @@ CASES = [
     # several tiles and z-chunks of the z-marching kernels, ragged edges
     ("periodic multi-tile 37x11x35", (35, 11, 37), False, {}),
     ("walls phi 1.3 multi-tile 33x10x34", (34, 10, 33), True, dict(wet_mode=1, wet_value=1.3)),
+    ("moving walls phi 1.4", (12, 8, 9), True, dict(wet_mode=1, wet_value=1.4, wall_u=(0.08, -0.03, -0.05, 0.02))),
+    ("moving walls, one fluid plane", (3, 8, 9), True, dict(wall_u=(0.1, 0.0, -0.1, 0.05))),
 ]
 
 
@@ -76,14 +78,14 @@ def test_adjoint_step_matches_oracle_reverse_mode(label, shape, walls, extra):
     assert ek < 1e-9 and en < 1e-9 and ew < 1e-9
 
 
-def _loss_setup(shape, walls, wet_mode, wet_value, steps):
+def _loss_setup(shape, walls, wet_mode, wet_value, steps, wall_u=(0.0, 0.0, 0.0, 0.0)):
     T = eos.temperature(0.7)
     nz, ny, nx = shape
     rho0 = droplet_rho(shape, T, walls=walls, radius=min(shape) / 3, noise=1e-2, seed=9)
     rl, rv = eos.maxwell(eos.PAPER["a"], eos.PAPER["b"], eos.PAPER["R"], T)
     tgt = rho0 + 1e-3 * (rl - rv) * inputs.uniform_noise(shape, 1.0, 12)
     cfg = lag.StepConfig(nx=nx, ny=ny, nz=nz, steps=steps, checkpoint_every=4, T=T, walls_z=int(walls),
-                         wet_mode=wet_mode)
+                         wet_mode=wet_mode, wall_u=wall_u)
     return rho0, tgt, cfg
 
 
@@ -97,12 +99,14 @@ def _gpu_loss(rho0, tgt, cfg, kappa, wet, walls):
     return float(((r - t)[sl] ** 2).sum())
 
 
-@pytest.mark.parametrize("walls,wet_mode,wet_value", [(False, 0, 1.0), (True, 1, 1.3), (True, 2, 0.6)])
-def test_end_to_end_gradients_vs_oracle_and_fd(walls, wet_mode, wet_value):
+@pytest.mark.parametrize("walls,wet_mode,wet_value,wall_u", [
+    (False, 0, 1.0, (0.0, 0.0, 0.0, 0.0)), (True, 1, 1.3, (0.0, 0.0, 0.0, 0.0)), (True, 2, 0.6, (0.0, 0.0, 0.0, 0.0)),
+    (True, 1, 1.3, (0.06, -0.02, -0.04, 0.03))])
+def test_end_to_end_gradients_vs_oracle_and_fd(walls, wet_mode, wet_value, wall_u):
     shape = (10, 8, 8) if walls else (8, 8, 8)
     steps = 12
-    rho0, tgt, cfg = _loss_setup(shape, walls, wet_mode, wet_value, steps)
-    say(f"end-to-end walls={walls} mode={wet_mode}")
+    rho0, tgt, cfg = _loss_setup(shape, walls, wet_mode, wet_value, steps, wall_u)
+    say(f"end-to-end walls={walls} mode={wet_mode} wall_u={wall_u}")
     # GPU adjoint through the autograd Function
     r0 = torch.tensor(rho0, device="cuda", requires_grad=True)
     kap = torch.tensor(0.02, dtype=DT, requires_grad=True)
@@ -113,7 +117,7 @@ def test_end_to_end_gradients_vs_oracle_and_fd(walls, wet_mode, wet_value):
     loss.backward()
     g_r0 = r0.grad.cpu()
     # oracle reverse mode through init + steps + loss
-    p = lbm.Params(shape[2], shape[1], shape[0], walls_z=walls, T=cfg.T, wet_mode=wet_mode)
+    p = lbm.Params(shape[2], shape[1], shape[0], walls_z=walls, T=cfg.T, wet_mode=wet_mode, wall_u=wall_u)
     rl, rv = p.coexistence()
     ko = torch.tensor(0.02, dtype=DT, requires_grad=True)
     wo = torch.tensor(wet_value, dtype=DT, requires_grad=True)
