@@ -95,8 +95,8 @@ typedef struct lbfe_params {
                             bounce-back; |u| <= 0.3; nonzero needs
                             walls_z = 1; 0 = resting walls */
     int32_t solid_mask;  /* 1: the solid nodes come from a voxel mask given
-                            by lbfe_set_solid (needs walls_z = 0, adjoint =
-                            0, resting walls); 0: none or the wall planes */
+                            by lbfe_set_solid (needs walls_z = 0 and resting
+                            walls); 0: none or the wall planes */
     /* Schedule.  None of these changes a result bit; 0 lets lbfe_create
      * choose per grid, and lbfe_get_params reports the choice made. */
     int32_t step_path;   /* LBFE_PATH_*: how one step is split into kernels */

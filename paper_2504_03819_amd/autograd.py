@@ -40,6 +40,7 @@ class StepConfig:
     corr4: int = 1
     omega: list = field(default_factory=lambda: [1.0] * 11)
     wall_u: tuple = (0.0, 0.0, 0.0, 0.0)  # moving walls: (ux, uy) bottom, top
+    solid: object = None       # optional solid voxel mask (nz, ny, nx), nonzero = solid
     u0: object = None          # optional (3, nz, ny, nx) initial velocity
     device: str = "cuda"
     stats: dict = field(default_factory=dict)   # filled with timing/memory info
@@ -59,7 +60,7 @@ class StepConfig:
                                kappa=float(kappa), walls_z=self.walls_z, wet_mode=self.wet_mode,
                                wet_value=float(wet_value), precision=self.precision, corr4=self.corr4,
                                omega=self.omega, wall_u=tuple(self.wall_u), adjoint=1,
-                               check_every=max(1, self.checkpoint_every))
+                               check_every=max(1, self.checkpoint_every), solid=self.solid)
 
 
 def reverse_binomial(sim, state_a, a, b, snapshots, stats=None):

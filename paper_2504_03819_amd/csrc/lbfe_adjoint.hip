@@ -31,6 +31,14 @@ namespace {
 
 template <int P> using real_t = typename Pol<P>::real;
 
+constexpr unsigned kSelfBit = 1u << kRest;  // neighbour word: the node itself is solid
+// a fluid node: inside the fluid planes, and not solid in a voxel mask
+__device__ inline bool fluid_node(const KP &kp, const Bufs &b, size_t n) {
+    if (kp.masked) return !(b.nbr[n] & kSelfBit);
+    const int z = (int)(n / kp.plane);
+    return z >= kp.z0 && z < kp.z1;
+}
+
 // Adjoint auxiliary arrays inside Bufs::abuf, in slots of N doubles.  The
 // slots marked (real) hold planes in the compute precision (three float
 // planes use half of their three slots): those values are formed in that
@@ -284,6 +292,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     const unsigned row = nb.row(0, 0);
     const Pops<P> fin(ft, kp);
     const Lam<real> lin(const_cast<void *>(lam_in), kp), lout(lam_out, kp);
+    // solid mask: bit i of the neighbour word marks a link that ends on a
+    // solid node (bounce-back); a solid node holds no lambda
+    const unsigned wm = kp.masked ? b.nbr[n] : 0u;
+    if (wm & kSelfBit) {
+#pragma unroll
+        for (int i = 0; i < 27; ++i) lout.st(i, row, (unsigned)x, (real)0);
+        return;
+    }
 
     // forward recomputation at x: the moments, kinematics and collision of
     // k_collide (the same device functions, so the same roundings)
@@ -323,7 +339,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     const bool wall_hi = kp.walls && z == kp.nz - 2;
     real l[27];
     const Pack4<real> *pk = (const Pack4<real> *)((const double *)b.abuf + A_PACK * (size_t)kp.N);
-    if constexpr (PEND && sizeof(real) == 8) {
+    auto bounce = [&](int i) {
+        const int cz = czi(i);
+        return kp.masked ? ((wm >> i) & 1u) != 0 : ((cz < 0 && wall_lo) || (cz > 0 && wall_hi));
+    };
+    if (PEND && (sizeof(real) == 8 || kp.masked)) {
         // FP64: the pending (rho_bar_total, j_bar) of each link's neighbour
         // with one vector load per link, beside the link's lambda (the
         // lane-shift form below needs more registers than an FP64 wave has
@@ -331,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
 #pragma unroll
         for (int i = 0; i < 27; ++i) {
             const int cz = czi(i);
-            if ((cz < 0 && wall_lo) || (cz > 0 && wall_hi))
+            if (bounce(i))
                 l[i] = lin.ld(26 - i, row, (unsigned)x) + final_term<real>(pk, 26 - i, n);
             else
                 l[i] = lin.ld(i, nb.row(cyi(i), cz), nb.xo(cxi(i))) +
@@ -341,13 +361,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
 #pragma unroll
         for (int i = 0; i < 27; ++i) {
             const int cz = czi(i);
-            if ((cz < 0 && wall_lo) || (cz > 0 && wall_hi))
+            if (bounce(i))
                 l[i] = lin.ld(26 - i, row, (unsigned)x);
             else
                 l[i] = lin.ld(i, nb.row(cyi(i), cz), nb.xo(cxi(i)));
         }
     }
-    if constexpr (PEND && sizeof(real) == 4) {
+    if (PEND && sizeof(real) == 4 && !kp.masked) {
         // The pending (rho_bar_total, j_bar) of the 27 neighbours, one row
         // (cy, cz) at a time: the x - 1 and x + 1 values are those of the
         // adjacent lanes (a wave holds consecutive nodes), loaded only by
@@ -477,6 +497,7 @@ template <int P> __global__ __launch_bounds__(ZCB) void k_adj_phi(KP kp, Bufs b,
         py *= 9.0;
         pz *= 9.0;
         const size_t n = (size_t)k * kp.plane + R.node;
+        if (kp.masked && (b.nbr[n] & kSelfBit)) return;  // solid: its source adjoints stay zero
         // forward quantities at x, rounded as the chain kernel rounds them:
         // u = (j + F/2) (1/rho), phi = c2 u with c2 = p_m - rho/3
         const double r = b.rho[n], mu = R.at(3, k, 0, 0);
@@ -591,7 +612,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_wall_gather(KP kp, const double 
 // per-node dL/dkappa = -mu_bar L[rho].  `mub` is the total mu_bar (solid
 // entries are ignored: the Laplacian's adjoint sees fluid mu_bar only).
 __global__ __launch_bounds__(ZCB) void k_adj_rho(KP kp, const double *mub, const double *rhob_local,
-                                                 const double *rho, double *rhobt, double *kapc, int cz) {
+                                                 const double *rho, double *rhobt, double *kapc, int cz,
+                                                 const unsigned *nbr) {
     __shared__ double lds[4][2][ZNR];
     int x0, y0, zs, ze;
     ztile(kp, cz, 0, kp.nz, x0, y0, zs, ze);
@@ -602,7 +624,6 @@ __global__ __launch_bounds__(ZCB) void k_adj_rho(KP kp, const double *mub, const
     R.zmask = 1u;  // mu_bar of solid planes reads as zero
     R.march(zs, ze, [&](int k) {
         if (!R.own) return;
-        const bool fluid = k >= kp.z0 && k < kp.z1;
         const double m0 = R.at(0, k, 0, 0);
         const double r0 = R.at(1, k, 0, 0);
         double lm = 0.0, lr = 0.0;
@@ -616,6 +637,7 @@ __global__ __launch_bounds__(ZCB) void k_adj_rho(KP kp, const double *mub, const
         lm *= 6.0;
         lr *= 6.0;
         const size_t n = (size_t)k * kp.plane + R.node;
+        const bool fluid = nbr ? !(nbr[n] & kSelfBit) : (k >= kp.z0 && k < kp.z1);
         double out = -kp.kappa * lm;
         if (fluid) {
             const double d = 1.0 - kp.b * r0;
@@ -671,12 +693,101 @@ __global__ __launch_bounds__(kBlock) void k_adj_wall_rho_solid(KP kp, const doub
     wetc[idx] = dwet * g;
 }
 
+// ---- solid voxel masks ------------------------------------------------------
+// The transposes of the mask path's wall averages (Eqs. (36)-(37) at every
+// solid node with a fluid neighbour, weights w_i of its fluid neighbours in
+// direction order) and of the window of Eq. (38), per node.
+
+// dst = src at fluid nodes, 0 at solid nodes (mu_bar as the Laplacian's
+// adjoint sees it)
+__global__ __launch_bounds__(kBlock) void k_adj_fluid_copy_m(KP kp, const unsigned *nbr, const double *src,
+                                                           double *dst) {
+    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= kp.N) return;
+    dst[n] = (nbr[n] & kSelfBit) ? 0.0 : src[n];
+}
+
+// weight sum of the wall average at solid node n (0: no fluid neighbour)
+__device__ inline double mask_den(unsigned w) {
+    double den = 0.0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i)
+        if (!(w & (1u << i))) den += wi(i);
+    return den;
+}
+
+// dst(y) += sum over the solid neighbours s = y + c_i of fluid y of
+// w_i / den(s) src(s)
+__global__ __launch_bounds__(kBlock) void k_adj_wall_gather_m(KP kp, const unsigned *nbr, const double *src,
+                                                            double *dst) {
+    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= kp.N) return;
+    const unsigned w = nbr[n];
+    if ((w & kSelfBit) || w == 0u) return;
+    int x, y, z;
+    decompose(kp, n, x, y, z);
+    const Nb nb(kp, x, y, z);
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        if (!(w & (1u << i))) continue;
+        const unsigned s = nb.at(cxi(i), cyi(i), czi(i));
+        acc += wi(i) / mask_den(nbr[s]) * src[s];
+    }
+    dst[n] += acc;
+}
+
+// Solid nodes: rho_ave_bar = W'(rho_ave) rho_bar(x_s) and the per-node
+// dL/d(wet_value) (active branch of Eq. (38)); 0 elsewhere.
+__global__ __launch_bounds__(kBlock) void k_adj_wall_rho_solid_m(KP kp, const unsigned *nbr, const double *rho,
+                                                               const double *rhobt, double *raveb, double *wetc) {
+    const unsigned n = blockIdx.x * kBlock + threadIdx.x;
+    if (n >= kp.N) return;
+    const unsigned w = nbr[n];
+    double rb = 0.0, wc = 0.0;
+    if (w & kSelfBit) {
+        int x, y, z;
+        decompose(kp, n, x, y, z);
+        const Nb nb(kp, x, y, z);
+        double num = 0.0, den = 0.0;
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            if (w & (1u << i)) continue;
+            const double wt = wi(i);
+            num += wt * rho[nb.at(cxi(i), cyi(i), czi(i))];
+            den += wt;
+        }
+        if (den > 0.0) {
+            const double rave = num / den, g = rhobt[n];
+            double dW = 1.0, dwet = 0.0;
+            if (rave >= kp.lo && rave <= kp.hi) {
+                if (kp.wet_mode == LBFE_WET_PHI) {
+                    const double v = kp.wet_value * rave;
+                    const bool inside = v >= kp.lo && v <= kp.hi;
+                    dW = inside ? kp.wet_value : 0.0;
+                    dwet = inside ? rave : 0.0;
+                } else if (kp.wet_mode == LBFE_WET_DELTA) {
+                    const double v = rave - kp.wet_value;
+                    const bool inside = v >= kp.lo && v <= kp.hi;
+                    dW = inside ? 1.0 : 0.0;
+                    dwet = inside ? -1.0 : 0.0;
+                }
+            }
+            rb = dW * g;
+            wc = dwet * g;
+        }
+    }
+    raveb[n] = rb;
+    wetc[n] = wc;
+}
+
 // lambda_i(t) = direct part + rho_bar_total + c_i . j_bar at fluid nodes.
 template <int P> __global__ __launch_bounds__(kBlock) void k_adj_final(KP kp, Bufs b, void *lam) {
     using real = real_t<P>;
     const unsigned idx = tile_id(kp) * kBlock + threadIdx.x;
     if (idx >= kp.nfluid) return;
     const unsigned n = (unsigned)kp.z0 * kp.plane + idx;
+    if (kp.masked && (b.nbr[n] & kSelfBit)) return;
     const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
     const Pack4<real> *pk = (const Pack4<real> *)((const double *)b.abuf + A_PACK * (size_t)kp.N);
     const Lam<real> L(lam, kp);
@@ -730,38 +841,37 @@ __global__ __launch_bounds__(kBlock) void k_adj_reduce_final(unsigned nblk, cons
 }
 
 // ---- seed and initialiser ---------------------------------------------------
-template <int P> __global__ __launch_bounds__(kBlock) void k_adj_seed(KP kp, const double *g, void *lam) {
+template <int P> __global__ __launch_bounds__(kBlock) void k_adj_seed(KP kp, Bufs b, const double *g, void *lam) {
     using real = real_t<P>;
     const unsigned n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= kp.N) return;
     const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
-    const int z = (int)(n / kp.plane);
-    const bool fluid = z >= kp.z0 && z < kp.z1;
+    const bool fluid = fluid_node(kp, b, n);
     const real v = fluid ? (real)g[n] : (real)0;
     const Lam<real> L(lam, kp);
 #pragma unroll
     for (int i = 0; i < 27; ++i) L.st(i, row, x, v);
 }
 
-template <int P> __global__ __launch_bounds__(kBlock) void k_adj_seed_pop(KP kp, const double *g, void *lam) {
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_adj_seed_pop(KP kp, Bufs b, const double *g, void *lam) {
     using real = real_t<P>;
     const unsigned n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= kp.N) return;
     const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
-    const int z = (int)(n / kp.plane);
-    const bool fluid = z >= kp.z0 && z < kp.z1;
+    const bool fluid = fluid_node(kp, b, n);
     const Lam<real> L(lam, kp);
 #pragma unroll
     for (int i = 0; i < 27; ++i) L.st(i, row, x, fluid ? (real)g[(size_t)i * kp.N + n] : (real)0);
 }
 
-template <int P> __global__ __launch_bounds__(kBlock) void k_adj_get(KP kp, const void *lam, double *out) {
+template <int P>
+__global__ __launch_bounds__(kBlock) void k_adj_get(KP kp, Bufs b, const void *lam, double *out) {
     using real = real_t<P>;
     const unsigned n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= kp.N) return;
     const unsigned row = n / (unsigned)kp.nx, x = n - row * (unsigned)kp.nx;
-    const int z = (int)(n / kp.plane);
-    const bool fluid = z >= kp.z0 && z < kp.z1;
+    const bool fluid = fluid_node(kp, b, n);
     const Lam<real> L(const_cast<void *>(lam), kp);
 #pragma unroll
     for (int i = 0; i < 27; ++i) out[(size_t)i * kp.N + n] = fluid ? (double)L.ld(i, row, x) : 0.0;
@@ -774,8 +884,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_init_local(KP kp, Bufs b, const 
     using real = real_t<P>;
     const unsigned n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= kp.N) return;
-    const int z = (int)(n / kp.plane);
-    const bool fluid = z >= kp.z0 && z < kp.z1;
+    const bool fluid = fluid_node(kp, b, n);
     const size_t N = kp.N;
     double *A = (double *)b.abuf;
     if (!fluid) {
@@ -803,11 +912,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_init_local(KP kp, Bufs b, const 
     A[A_MUB * N + n] = pmb / 3.0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_adj_init_out(KP kp, const double *rhobt, double *out) {
+__global__ __launch_bounds__(kBlock) void k_adj_init_out(KP kp, Bufs b, const double *rhobt, double *out) {
     const unsigned n = blockIdx.x * kBlock + threadIdx.x;
     if (n >= kp.N) return;
-    const int z = (int)(n / kp.plane);
-    out[n] = (z >= kp.z0 && z < kp.z1) ? rhobt[n] : 0.0;
+    out[n] = fluid_node(kp, b, n) ? rhobt[n] : 0.0;
 }
 
 template <class Fn> hipError_t dispatch(int prec, Fn &&fn) {
@@ -834,18 +942,34 @@ hipError_t chain_tail(hipStream_t s, const KP &kp, const Bufs &b, bool with_grad
         k_adj_mu<<<gall, ZCB, 0, s>>>(kp, b, kZChunk);
         mub_tot = A + A_MUBT * N;
     }
-    if (kp.walls) k_adj_wall_gather<<<gw, kBlock, 0, s>>>(kp, mub_tot, mub_tot);
-    k_adj_rho<<<gall, ZCB, 0, s>>>(kp, mub_tot, A + A_RHOB * N, b.rho, A + A_RHOBT * N, A + A_KAPC * N, kZChunk);
     const double *wetc = nullptr;
-    if (kp.walls) {
-        k_adj_wall_rho_solid<<<gw, kBlock, 0, s>>>(kp, b.rho, A + A_RHOBT * N, A + A_RAVEB * N, A + A_WETC * N);
-        k_adj_wall_gather<<<gw, kBlock, 0, s>>>(kp, A + A_RAVEB * N, A + A_RHOBT * N);
+    unsigned nwet = 0;
+    if (kp.masked) {
+        // mu_bar of the solid nodes back to their fluid neighbours (Eq. (36)),
+        // then the Laplacian's adjoint with mu_bar zero at solid nodes
+        k_adj_wall_gather_m<<<gN, kBlock, 0, s>>>(kp, b.nbr, mub_tot, mub_tot);
+        k_adj_fluid_copy_m<<<gN, kBlock, 0, s>>>(kp, b.nbr, mub_tot, A + A_MUB * N);
+        k_adj_rho<<<gall, ZCB, 0, s>>>(kp, A + A_MUB * N, A + A_RHOB * N, b.rho, A + A_RHOBT * N, A + A_KAPC * N,
+                                       kZChunk, b.nbr);
+        k_adj_wall_rho_solid_m<<<gN, kBlock, 0, s>>>(kp, b.nbr, b.rho, A + A_RHOBT * N, A + A_RAVEB * N,
+                                                     A + A_WETC * N);
+        k_adj_wall_gather_m<<<gN, kBlock, 0, s>>>(kp, b.nbr, A + A_RAVEB * N, A + A_RHOBT * N);
         wetc = A + A_WETC * N;
+        nwet = (unsigned)N;
+    } else {
+        if (kp.walls) k_adj_wall_gather<<<gw, kBlock, 0, s>>>(kp, mub_tot, mub_tot);
+        k_adj_rho<<<gall, ZCB, 0, s>>>(kp, mub_tot, A + A_RHOB * N, b.rho, A + A_RHOBT * N, A + A_KAPC * N, kZChunk,
+                                       nullptr);
+        if (kp.walls) {
+            k_adj_wall_rho_solid<<<gw, kBlock, 0, s>>>(kp, b.rho, A + A_RHOBT * N, A + A_RAVEB * N, A + A_WETC * N);
+            k_adj_wall_gather<<<gw, kBlock, 0, s>>>(kp, A + A_RAVEB * N, A + A_RHOBT * N);
+            wetc = A + A_WETC * N;
+            nwet = 2u * (unsigned)kp.plane;
+        }
     }
     double *part = b.agrad + 8;
     const unsigned gr = gN < kReduceBlocks ? gN : kReduceBlocks;
-    k_adj_reduce_part<<<gr, kBlock, 0, s>>>((unsigned)N, A + A_KAPC * N, 2u * (unsigned)kp.plane, wetc, nuc,
-                                            part);
+    k_adj_reduce_part<<<gr, kBlock, 0, s>>>((unsigned)N, A + A_KAPC * N, nwet, wetc, nuc, part);
     k_adj_reduce_final<<<1, kBlock, 0, s>>>(gr, part, b.agrad);
     return hipGetLastError();
 }
@@ -863,7 +987,7 @@ hipError_t launch_adj_seed(hipStream_t s, int prec, const KP &kp, const Bufs &b,
     if (e != hipSuccess) return e;
     return dispatch(prec, [&](auto pc) {
         constexpr int P = decltype(pc)::value;
-        k_adj_seed<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, g, b.lam[lcur]);
+        k_adj_seed<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, b, g, b.lam[lcur]);
         return hipGetLastError();
     });
 }
@@ -875,7 +999,7 @@ hipError_t launch_adj_seed_pop(hipStream_t s, int prec, const KP &kp, const Bufs
     if (e != hipSuccess) return e;
     return dispatch(prec, [&](auto pc) {
         constexpr int P = decltype(pc)::value;
-        k_adj_seed_pop<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, g, b.lam[lcur]);
+        k_adj_seed_pop<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, b, g, b.lam[lcur]);
         return hipGetLastError();
     });
 }
@@ -883,7 +1007,7 @@ hipError_t launch_adj_seed_pop(hipStream_t s, int prec, const KP &kp, const Bufs
 hipError_t launch_adj_get(hipStream_t s, int prec, const KP &kp, const Bufs &b, int lcur, double *out) {
     return dispatch(prec, [&](auto pc) {
         constexpr int P = decltype(pc)::value;
-        k_adj_get<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, b.lam[lcur], out);
+        k_adj_get<P><<<nblocks(kp.N), kBlock, 0, s>>>(kp, b, b.lam[lcur], out);
         return hipGetLastError();
     });
 }
@@ -931,7 +1055,7 @@ hipError_t launch_adj_init(hipStream_t s, int prec, const KP &kp, const Bufs &b,
         k_adj_init_local<P><<<gN, kBlock, 0, s>>>(kp, b, b.lam[lcur], u0);
         hipError_t r = chain_tail(s, kp, b, false, nullptr);
         if (r != hipSuccess) return r;
-        k_adj_init_out<<<gN, kBlock, 0, s>>>(kp, (const double *)b.abuf + A_RHOBT * (size_t)kp.N, out);
+        k_adj_init_out<<<gN, kBlock, 0, s>>>(kp, b, (const double *)b.abuf + A_RHOBT * (size_t)kp.N, out);
         return hipGetLastError();
     });
 }

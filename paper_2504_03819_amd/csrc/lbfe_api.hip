@@ -120,7 +120,6 @@ std::string validate(const lbfe_params &p) {
     if (moving && !p.walls_z) return "moving walls need walls_z = 1";
     if (p.solid_mask != 0 && p.solid_mask != 1) return "solid_mask must be 0 or 1";
     if (p.solid_mask && p.walls_z) return "solid_mask replaces walls_z (put the planes into the mask)";
-    if (p.solid_mask && p.adjoint) return "the adjoint does not cover solid masks";
     if (p.step_path < LBFE_AUTO || p.step_path > LBFE_PATH_STATE) return "unknown step_path";
     if (p.step_path == LBFE_PATH_STATE) {  // the moment state: the paper's rates, storage and boundaries
         if (p.precision != LBFE_FP64 && p.precision != LBFE_FP32) return "the moment-state path stores FP64 or FP32 only";

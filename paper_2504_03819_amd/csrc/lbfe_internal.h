@@ -120,6 +120,7 @@ hipError_t launch_step_mask(hipStream_t s, int prec, const KP &kp, const Bufs &b
 hipError_t launch_init_mask(hipStream_t s, int prec, const KP &kp, const Bufs &b, int cur, const double *rho0,
                             const double *u0);
 hipError_t launch_check_rho0_mask(hipStream_t s, const KP &kp, const Bufs &b, const double *rho0, int *flag);
+hipError_t launch_init_aux_mask(hipStream_t s, const KP &kp, const Bufs &b, const double *rho0);
 
 // adjoint (lbfe_adjoint.hip)
 size_t adjoint_aux_bytes(int prec, size_t N);

@@ -611,6 +611,7 @@ hipError_t launch_set_pop(hipStream_t s, int prec, const KP &kp, const Bufs &b, 
 }
 
 hipError_t launch_init_aux(hipStream_t s, const KP &kp, const Bufs &b, const double *rho0) {
+    if (kp.masked) return launch_init_aux_mask(s, kp, b, rho0);
     const unsigned gf = nblocks(kp.nfluid), gw = nblocks(2 * (size_t)kp.plane);
     k_copy_fluid<<<gf, kBlock, 0, s>>>(kp, rho0, b.rho);
     if (kp.walls) k_wall_rho<<<gw, kBlock, 0, s>>>(kp, b.rho);

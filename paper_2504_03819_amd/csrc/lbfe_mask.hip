@@ -416,6 +416,14 @@ hipError_t launch_init_mask(hipStream_t s, int prec, const KP &kp, const Bufs &b
     });
 }
 
+hipError_t launch_init_aux_mask(hipStream_t s, const KP &kp, const Bufs &b, const double *rho0) {
+    const unsigned g = nblocks(kp.N);
+    k_copy_fluid_m<<<g, kBlock, 0, s>>>(kp, b.nbr, rho0, b.rho);
+    k_wall_rho_m<<<g, kBlock, 0, s>>>(kp, b.nbr, b.rho);
+    k_mu_m<<<g, kBlock, 0, s>>>(kp, b.nbr, b.rho, b.mu);
+    return hipGetLastError();
+}
+
 hipError_t launch_check_rho0_mask(hipStream_t s, const KP &kp, const Bufs &b, const double *rho0, int *flag) {
     k_check_rho_m<<<nblocks(kp.N), kBlock, 0, s>>>(kp, b.nbr, rho0, flag);
     return hipGetLastError();

@@ -70,7 +70,7 @@ def test_coexistence_matches_oracle_maxwell():
     dict(nx=2048, ny=2048, nz=1024), dict(nx=32768, ny=16384, nz=1),
     dict(wall_u=(0.1, 0.0, 0.0, 0.0)), dict(walls_z=1, wall_u=(0.0, 0.0, 0.31, 0.0)),
     dict(walls_z=1, wall_u=(float("nan"), 0.0, 0.0, 0.0)),
-    dict(solid_mask=2), dict(solid_mask=1, walls_z=1), dict(solid_mask=1, adjoint=1),
+    dict(solid_mask=2), dict(solid_mask=1, walls_z=1),
     # the moment-state path: the paper's unit rates, FP64/FP32, resting walls, no mask
     dict(step_path=4), dict(step_path=lbfe.PATH_STATE, precision=lbfe.FP16_DEV),
     dict(step_path=lbfe.PATH_STATE, precision=lbfe.FP16_DEV_F0FP32),
