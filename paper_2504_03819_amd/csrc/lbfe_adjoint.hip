@@ -20,6 +20,12 @@
 //                   is read out; between adjoint steps this term is added by
 //                   the next step's gather instead
 //   k_adj_reduce*   deterministic parameter-gradient accumulation
+// With a solid voxel mask the collision adjoint takes its bounce-back links
+// from the neighbour words, solid nodes hold no lambda and no source
+// adjoints, and the wall averages and window of every solid node are
+// transposed per node (k_adj_wall_gather_m, k_adj_wall_rho_solid_m).  With
+// moving walls the collision adjoint also transposes the wall-velocity term
+// of the reflected populations.
 #include <type_traits>
 
 #include "lbfe_device.h"
