@@ -150,3 +150,19 @@ def test_state_path_large_sampled_against_two_pass():
     a, b = (s.get_state() for s in sims)
     assert torch.equal(a, b)
     say("256^3 fp32: state path equals two-pass after 10 steps")
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_state_path_long_run_equals_two_pass(form):
+    """500 steps in one call (498 of them inside the state form) on the 64^3
+    stationary-droplet setup with a small flow, then 1 and 7 more: the same
+    bits as the two-pass path."""
+    T = eos.temperature(0.85)
+    shape = (64, 64, 64)
+    sims = _pair(form, shape, False, {}, T)
+    _init(sims, shape, False, T, seed=13)
+    for n in (500, 1, 7):
+        for s in sims:
+            s.step(n)
+        assert torch.equal(sims[0].get_state(), sims[1].get_state()), (form, n)
+    say(f"64^3 {form}: state path equals two-pass after 508 steps")
