@@ -4,7 +4,9 @@ Workload (default): the largest single-GPU configuration, the two-droplet
 head-on collision, a periodic 512^3 box at 0.85 T_c with two droplets of
 radius 64 whose centres are 160 lattice units apart along x, approaching at
 -+0.04, stepped in FP64 (the headline line) and, as extra fields, in the
-FP32 and FP16-deviation (rest population in FP32) storage forms.
+FP32 and FP16-deviation (rest population in FP32) storage forms and on the
+moment-state path in FP64 and FP32 (`fp64_state`, `fp32_state`: 16 numbers
+per node, 32 S algorithmic bytes).
 
 Prints ONE JSON line.  `value` is whole-job MLUPS (fluid nodes x steps /
 s / 1e6) of the FP64 form, measured with HIP events around K steps on the
@@ -693,7 +695,7 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="collision")
-    ap.add_argument("--forms", default="fp64,fp32,fp16dev_f0fp32",
+    ap.add_argument("--forms", default="fp64,fp32,fp16dev_f0fp32,fp64_state,fp32_state",
                     help="storage forms; the first is the headline (fp16dev is reported with valid: false)")
     ap.add_argument("--timed-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
