@@ -443,12 +443,6 @@ __device__ inline double collide_to_state(const KP &kp, real (&f)[27], double mu
     real jx, jy, jz;
     moments(f, rd, jx, jy, jz);
     const Kin<real> kin = kinematics(kp, rd, jx, jy, jz, Fx, Fy, Fz, mu);
-    real q220, q202, q022;
-    q4_of(kp, q200, q020, q002, q220, q202, q022);
-    Rates<real> R;
-#pragma unroll
-    for (int k = 0; k < 11; ++k) R.w[k] = (real)kp.om[k];
-    R.w[1] = kin.om1;
     cm_forward(f, kin.ux, kin.uy, kin.uz);
     const Dev2<real> D = dev2(f, kin.om1, q200, q020, q002);
     const real one = 1;

@@ -116,7 +116,6 @@ __global__ __launch_bounds__(NT) void k_mstate(KP kp, const void *sin_q, void *o
     // are also stored to plane L at offset v (kOOB: not stored).
     auto gather = [&](auto cc, bool refl, real(&val)[9], unsigned v, unsigned v0, const void *Lp, int z) {
         constexpr int c = decltype(cc)::value;
-        [[maybe_unused]] const LatPlane<P> L(Lp, kp, z);
 #pragma unroll
         for (int cx = -1; cx <= 1; ++cx)
 #pragma unroll
@@ -126,7 +125,10 @@ __global__ __launch_bounds__(NT) void k_mstate(KP kp, const void *sin_q, void *o
                 const bool rf = c != 0 && refl;
                 const int kk = rf ? oc : oc - cy * G::WX - cx;
                 val[jj] = rf ? pl.get(ir, kk) : pl.get(in, kk);
-                if constexpr (MODE == kPops) pl.store(L, rf ? 26 - ir : in, rf ? ir : in, kk, v, v0);
+                if constexpr (MODE == kPops) {
+                    const LatPlane<P> L(Lp, kp, z);
+                    pl.store(L, rf ? 26 - ir : in, rf ? ir : in, kk, v, v0);
+                }
             }
     };
     // moment partials of one layer in the order of moments()
