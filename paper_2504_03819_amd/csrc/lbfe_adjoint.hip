@@ -285,7 +285,7 @@ template <int P> __global__ __launch_bounds__(kBlock) void k_adj_pack(KP kp, Buf
 // PEND: lam_in holds only the direct part of lambda(t+1); its last term is
 // added during the gather from the (rho_bar_total, j_bar) pack that the
 // previous adjoint step left (this kernel does not write it).
-template <int P, bool PEND>
+template <int P, bool PEND, bool MASK>
 __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const void *ft, const void *lam_in,
                                                         void *lam_out) {
     using real = real_t<P>;
@@ -300,8 +300,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     const Lam<real> lin(const_cast<void *>(lam_in), kp), lout(lam_out, kp);
     // solid mask: bit i of the neighbour word marks a link that ends on a
     // solid node (bounce-back); a solid node holds no lambda
-    const unsigned wm = kp.masked ? b.nbr[n] : 0u;
-    if (wm & kSelfBit) {
+    const unsigned wm = MASK ? b.nbr[n] : 0u;
+    if (MASK && (wm & kSelfBit)) {
 #pragma unroll
         for (int i = 0; i < 27; ++i) lout.st(i, row, (unsigned)x, (real)0);
         return;
@@ -347,9 +347,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     const Pack4<real> *pk = (const Pack4<real> *)((const double *)b.abuf + A_PACK * (size_t)kp.N);
     auto bounce = [&](int i) {
         const int cz = czi(i);
-        return kp.masked ? ((wm >> i) & 1u) != 0 : ((cz < 0 && wall_lo) || (cz > 0 && wall_hi));
+        if constexpr (MASK) return ((wm >> i) & 1u) != 0;
+        return (cz < 0 && wall_lo) || (cz > 0 && wall_hi);
     };
-    if (PEND && (sizeof(real) == 8 || kp.masked)) {
+    if constexpr (PEND && (sizeof(real) == 8 || MASK)) {
         // FP64: the pending (rho_bar_total, j_bar) of each link's neighbour
         // with one vector load per link, beside the link's lambda (the
         // lane-shift form below needs more registers than an FP64 wave has
@@ -373,7 +374,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
                 l[i] = lin.ld(i, nb.row(cyi(i), cz), nb.xo(cxi(i)));
         }
     }
-    if (PEND && sizeof(real) == 4 && !kp.masked) {
+    if constexpr (PEND && sizeof(real) == 4 && !MASK) {
         // The pending (rho_bar_total, j_bar) of the 27 neighbours, one row
         // (cy, cz) at a time: the x - 1 and x + 1 values are those of the
         // adjacent lanes (a wave holds consecutive nodes), loaded only by
@@ -468,7 +469,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
 // phi_bar_a = transpose of Q_a = -9 sum_i w_i c_ia phi_a(x + c_i)
 // = 9 sum_i w_i c_ia Q_bar_a(x + c_i), then back through
 // phi = (p_m - rho/3) u, u = (j + F/2)/rho, F = (1/3 - rho) G, at fluid nodes.
-template <int P> __global__ __launch_bounds__(ZCB) void k_adj_phi(KP kp, Bufs b, int cz) {
+template <int P, bool MASK> __global__ __launch_bounds__(ZCB) void k_adj_phi(KP kp, Bufs b, int cz) {
     using real = real_t<P>;
     __shared__ double lds[4][4][ZNR];
     int x0, y0, zs, ze;
@@ -503,7 +504,9 @@ template <int P> __global__ __launch_bounds__(ZCB) void k_adj_phi(KP kp, Bufs b,
         py *= 9.0;
         pz *= 9.0;
         const size_t n = (size_t)k * kp.plane + R.node;
-        if (kp.masked && (b.nbr[n] & kSelfBit)) return;  // solid: its source adjoints stay zero
+        if constexpr (MASK) {
+            if (b.nbr[n] & kSelfBit) return;  // solid: its source adjoints stay zero
+        }
         // forward quantities at x, rounded as the chain kernel rounds them:
         // u = (j + F/2) (1/rho), phi = c2 u with c2 = p_m - rho/3
         const double r = b.rho[n], mu = R.at(3, k, 0, 0);
@@ -617,6 +620,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_wall_gather(KP kp, const double 
 // rho_bar_total(y) = [fluid: rho_bar + mu_bar mu0'(rho)] - kappa L[mu_bar_fluid](y);
 // per-node dL/dkappa = -mu_bar L[rho].  `mub` is the total mu_bar (solid
 // entries are ignored: the Laplacian's adjoint sees fluid mu_bar only).
+template <bool MASK>
 __global__ __launch_bounds__(ZCB) void k_adj_rho(KP kp, const double *mub, const double *rhob_local,
                                                  const double *rho, double *rhobt, double *kapc, int cz,
                                                  const unsigned *nbr) {
@@ -643,7 +647,11 @@ __global__ __launch_bounds__(ZCB) void k_adj_rho(KP kp, const double *mub, const
         lm *= 6.0;
         lr *= 6.0;
         const size_t n = (size_t)k * kp.plane + R.node;
-        const bool fluid = nbr ? !(nbr[n] & kSelfBit) : (k >= kp.z0 && k < kp.z1);
+        bool fluid;
+        if constexpr (MASK)
+            fluid = !(nbr[n] & kSelfBit);
+        else
+            fluid = k >= kp.z0 && k < kp.z1;
         double out = -kp.kappa * lm;
         if (fluid) {
             const double d = 1.0 - kp.b * r0;
@@ -955,8 +963,8 @@ hipError_t chain_tail(hipStream_t s, const KP &kp, const Bufs &b, bool with_grad
         // then the Laplacian's adjoint with mu_bar zero at solid nodes
         k_adj_wall_gather_m<<<gN, kBlock, 0, s>>>(kp, b.nbr, mub_tot, mub_tot);
         k_adj_fluid_copy_m<<<gN, kBlock, 0, s>>>(kp, b.nbr, mub_tot, A + A_MUB * N);
-        k_adj_rho<<<gall, ZCB, 0, s>>>(kp, A + A_MUB * N, A + A_RHOB * N, b.rho, A + A_RHOBT * N, A + A_KAPC * N,
-                                       kZChunk, b.nbr);
+        k_adj_rho<true><<<gall, ZCB, 0, s>>>(kp, A + A_MUB * N, A + A_RHOB * N, b.rho, A + A_RHOBT * N,
+                                             A + A_KAPC * N, kZChunk, b.nbr);
         k_adj_wall_rho_solid_m<<<gN, kBlock, 0, s>>>(kp, b.nbr, b.rho, A + A_RHOBT * N, A + A_RAVEB * N,
                                                      A + A_WETC * N);
         k_adj_wall_gather_m<<<gN, kBlock, 0, s>>>(kp, b.nbr, A + A_RAVEB * N, A + A_RHOBT * N);
@@ -964,8 +972,8 @@ hipError_t chain_tail(hipStream_t s, const KP &kp, const Bufs &b, bool with_grad
         nwet = (unsigned)N;
     } else {
         if (kp.walls) k_adj_wall_gather<<<gw, kBlock, 0, s>>>(kp, mub_tot, mub_tot);
-        k_adj_rho<<<gall, ZCB, 0, s>>>(kp, mub_tot, A + A_RHOB * N, b.rho, A + A_RHOBT * N, A + A_KAPC * N, kZChunk,
-                                       nullptr);
+        k_adj_rho<false><<<gall, ZCB, 0, s>>>(kp, mub_tot, A + A_RHOB * N, b.rho, A + A_RHOBT * N, A + A_KAPC * N,
+                                              kZChunk, nullptr);
         if (kp.walls) {
             k_adj_wall_rho_solid<<<gw, kBlock, 0, s>>>(kp, b.rho, A + A_RHOBT * N, A + A_RAVEB * N, A + A_WETC * N);
             k_adj_wall_gather<<<gw, kBlock, 0, s>>>(kp, A + A_RAVEB * N, A + A_RHOBT * N);
@@ -1030,11 +1038,19 @@ hipError_t launch_adj_step(hipStream_t s, int prec, const KP &kp, const Bufs &b,
     double *A = (double *)b.abuf;
     return dispatch(prec, [&](auto pc) {
         constexpr int P = decltype(pc)::value;
-        if (pending)
-            k_adj_collide<P, true><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
-        else
-            k_adj_collide<P, false><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
-        k_adj_phi<P><<<zgrid(kp, kp.z0, kp.z1), ZCB, 0, s>>>(kp, b, kZChunk);
+        if (kp.masked) {
+            if (pending)
+                k_adj_collide<P, true, true><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
+            else
+                k_adj_collide<P, false, true><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
+            k_adj_phi<P, true><<<zgrid(kp, kp.z0, kp.z1), ZCB, 0, s>>>(kp, b, kZChunk);
+        } else {
+            if (pending)
+                k_adj_collide<P, true, false><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
+            else
+                k_adj_collide<P, false, false><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
+            k_adj_phi<P, false><<<zgrid(kp, kp.z0, kp.z1), ZCB, 0, s>>>(kp, b, kZChunk);
+        }
         hipError_t r = chain_tail(s, kp, b, true, A + A_NUC * (size_t)kp.N);
         if (r != hipSuccess) return r;
         k_adj_pack<P><<<gf, kBlock, 0, s>>>(kp, b);
