@@ -80,7 +80,7 @@ template <int W> __device__ inline double smooth2(const double *g, int c) {
     return A1 * r0 + A0 * r1 + A1 * r2;
 }
 
-template <int P>
+template <int P, bool WALLS>
 __global__ __launch_bounds__(CB) void k_chain(KP kp, const double *__restrict__ rho, const double *__restrict__ mu0,
                                               const void *jq, double *__restrict__ mu, void *Fq, void *Qq, int cz) {
     using real = typename Pol<P>::real;
@@ -107,8 +107,10 @@ __global__ __launch_bounds__(CB) void k_chain(KP kp, const double *__restrict__ 
     real *F = (real *)Fq;
     real *Q = (real *)Qq;
 
-    auto fluid = [&](int p) { return kp.walls ? (p >= 1 && p <= kp.nz - 2) : true; };
-    auto valid = [&](int p) { return !kp.walls || (p >= 0 && p <= kp.nz - 1); };
+    // WALLS: solid planes z = 0 and z = nz-1 (kp.walls; a template argument,
+    // so the periodic kernel carries none of the wall code)
+    auto fluid = [&](int p) { return WALLS ? (p >= 1 && p <= kp.nz - 2) : true; };
+    auto valid = [&](int p) { return !WALLS || (p >= 0 && p <= kp.nz - 1); };
     auto interior = [&](int a, int b) { return x0 + a < kp.nx && y0 + b < kp.ny; };
     // plane indices wrap periodically; inside the march they advance by one
     auto next = [&](int g) { return g + 1 == kp.nz ? 0 : g + 1; };
@@ -233,7 +235,7 @@ __global__ __launch_bounds__(CB) void k_chain(KP kp, const double *__restrict__ 
             const int s3 = slot3(q3), s2 = slot3(p);
             const bool do_mu = p >= zs - 2 && fluid(p);
             const bool out_plane = p >= zs && p < ze;
-            const bool full = kp.walls && (p == 1 || p == kp.nz - 2);
+            const bool full = WALLS && (p == 1 || p == kp.nz - 2);
             const __amdgpu_buffer_rsrc_t rmu = plane_rsrc(mu + pbase(g2), pbytes8);
 #pragma unroll
             for (int m = 0; m < MM; ++m) {
@@ -257,11 +259,13 @@ __global__ __launch_bounds__(CB) void k_chain(KP kp, const double *__restrict__ 
                 bstore(v, rmu, ioff(out, a - 3, b - 3, 8u));
             }
             issue_mu0(g3);
-            if (kp.walls && p == 1 && p >= zs - 2) {  // bottom solid plane, from the first fluid plane
-                __syncthreads();
-                wall_mu(0, 1, zs - 1 == 0);
-            } else if (kp.walls && p == kp.nz - 1 && p >= zs - 2) {  // top solid plane
-                wall_mu(p, p - 1, p == ze);
+            if constexpr (WALLS) {
+                if (p == 1 && p >= zs - 2) {  // bottom solid plane, from the first fluid plane
+                    __syncthreads();
+                    wall_mu(0, 1, zs - 1 == 0);
+                } else if (p == kp.nz - 1 && p >= zs - 2) {  // top solid plane
+                    wall_mu(p, p - 1, p == ze);
+                }
             }
         }
         __syncthreads();
@@ -293,7 +297,7 @@ __global__ __launch_bounds__(CB) void k_chain(KP kp, const double *__restrict__ 
                     if (do_abc) abc(p2, m, Ar[m][2], Br[m][2], Cr[m][2]);
                     // the bottom solid plane's mu only exists from the step
                     // that evaluated the first fluid plane: refresh its entry
-                    if (do_abc && kp.walls && p2 == 1) abc(0, m, Ar[m][1], Br[m][1], Cr[m][1]);
+                    if (do_abc && WALLS && p2 == 1) abc(0, m, Ar[m][1], Br[m][1], Cr[m][1]);
                     if (do_phi && !fl1) sp[0][r] = sp[1][r] = sp[2][r] = (real)0;
                     if (do_phi && fl1) {
                         const double gx = 0.5 * (A1 * Ar[m][0] + A0 * Ar[m][1] + A1 * Ar[m][2]);
@@ -396,11 +400,18 @@ hipError_t launch_chain(hipStream_t s, int prec, const KP &kp, const Bufs &b) {
     const int cz = chain_chunk_for(kp);
     const int nzf = kp.z1 - kp.z0;
     const dim3 grid(ntx * nty, (nzf + cz - 1) / cz);
+    auto go = [&](auto pc) {
+        constexpr int P = decltype(pc)::value;
+        if (kp.walls)
+            k_chain<P, true><<<grid, CB, 0, s>>>(kp, b.rho, b.mu0, b.j, b.mu, b.F, b.Q, cz);
+        else
+            k_chain<P, false><<<grid, CB, 0, s>>>(kp, b.rho, b.mu0, b.j, b.mu, b.F, b.Q, cz);
+    };
     switch (prec) {
-        case LBFE_FP64: k_chain<LBFE_FP64><<<grid, CB, 0, s>>>(kp, b.rho, b.mu0, b.j, b.mu, b.F, b.Q, cz); break;
-        case LBFE_FP32: k_chain<LBFE_FP32><<<grid, CB, 0, s>>>(kp, b.rho, b.mu0, b.j, b.mu, b.F, b.Q, cz); break;
-        case LBFE_FP16_DEV: k_chain<LBFE_FP16_DEV><<<grid, CB, 0, s>>>(kp, b.rho, b.mu0, b.j, b.mu, b.F, b.Q, cz); break;
-        default: k_chain<LBFE_FP16_DEV_F0FP32><<<grid, CB, 0, s>>>(kp, b.rho, b.mu0, b.j, b.mu, b.F, b.Q, cz); break;
+        case LBFE_FP64: go(std::integral_constant<int, LBFE_FP64>{}); break;
+        case LBFE_FP32: go(std::integral_constant<int, LBFE_FP32>{}); break;
+        case LBFE_FP16_DEV: go(std::integral_constant<int, LBFE_FP16_DEV>{}); break;
+        default: go(std::integral_constant<int, LBFE_FP16_DEV_F0FP32>{}); break;
     }
     return hipGetLastError();
 }
