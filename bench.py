@@ -73,6 +73,11 @@ def kernel_source_hash():
 # drifts by 5.9e-2 per 1000 steps and long runs leave the EOS domain)
 INVALID_FORMS = {"fp16dev": "all-FP16 storage: mass drift 5.9e-2 per 1000 steps, diverges in long runs"}
 STEP_KERNELS = ("k_moments", "k_chain", "k_collide", "k_fused", "k_wall_rho", "k_wall_move", "k_mstate")
+ADJ_COUNTERS = os.path.join(ROOT, "profiles", "adjoint_counters.json")
+# kernels of one adjoint step with the forward fields kept (the seed, the
+# read-out and the initialiser's adjoint are not part of a step)
+ADJ_STEP_KERNELS = ("k_adj_collide", "k_adj_phi", "k_adj_mu", "k_adj_rho", "k_adj_wall", "k_adj_pack",
+                    "k_adj_reduce")
 PATH_NAMES = {1: "two-pass", 2: "fused", 3: "state"}
 DOMINANT = {"two-pass": "k_collide (collide + push-stream)",
             "fused": "k_fused (collide + stream + next-step moments)",
@@ -689,6 +694,54 @@ def summarize_counters(fetch_csv, write_csv, form, workload_name, out_path):
     print(json.dumps({k: v for k, v in res.items() if k != "kernels"}))
 
 
+def summarize_adjoint_counters(fetch_csv, write_csv, out_path):
+    """Calibrated HBM bytes per adjoint step from two rocprofv3 --pmc passes
+    (FETCH_SIZE, then WRITE_SIZE) of `bench.py --adjoint-only --copy-calib`:
+    every dispatch of the adjoint-step kernels summed, over the number of
+    collision-adjoint dispatches (one per adjoint step)."""
+    import csv
+    rows = {}
+    for path, counter in ((fetch_csv, "FETCH_SIZE"), (write_csv, "WRITE_SIZE")):
+        with open(path) as fh:
+            rows[counter] = [(r["Kernel_Name"], float(r["Counter_Value"])) for r in csv.DictReader(fh)
+                             if r.get("Counter_Name") == counter]
+    gib_kib = (1 << 30) / 1024.0
+    fac = {}
+    for counter, rs in rows.items():
+        copies = [v for k, v in rs if "copybuffer" in k.lower()]
+        if not copies:
+            raise SystemExit(f"no copy dispatch in the {counter} pass")
+        fac[counter] = gib_kib / max(copies)
+    steps = sum(1 for k, _ in rows["FETCH_SIZE"] if "k_adj_collide" in k)
+    if steps == 0:
+        raise SystemExit("no collision-adjoint dispatch in the run")
+    per_kernel = {}
+    for counter, rs in rows.items():
+        for k, v in rs:
+            if any(s in k for s in ADJ_STEP_KERNELS):
+                name = re.sub(r"^void |lbfe::\(anonymous namespace\)::|\(lbfe::KP.*$", "", k)
+                d = per_kernel.setdefault(name, {"FETCH_SIZE": 0.0, "WRITE_SIZE": 0.0})
+                d[counter] += v * fac[counter] * 1024.0 / steps
+    res = {"source_hash": kernel_source_hash(), "adjoint_steps": steps,
+           "copy_fetch_factor": fac["FETCH_SIZE"], "copy_write_factor": fac["WRITE_SIZE"],
+           "bytes_per_adjoint_step": sum(d["FETCH_SIZE"] + d["WRITE_SIZE"] for d in per_kernel.values()),
+           "kernels_bytes_per_step": per_kernel}
+    json.dump(res, open(out_path, "w"), indent=1)
+    print(json.dumps({k: v for k, v in res.items() if k != "kernels_bytes_per_step"}))
+
+
+def adjoint_achieved(adj):
+    """Counter-based HBM fraction of an adjoint step (the committed counter
+    file, while it matches the sources) added to the adjoint leg."""
+    if not os.path.exists(ADJ_COUNTERS):
+        return
+    c = json.load(open(ADJ_COUNTERS))
+    if c.get("source_hash") != kernel_source_hash():
+        return
+    adj["traffic_per_step"] = c["bytes_per_adjoint_step"]
+    adj["achieved_frac"] = c["bytes_per_adjoint_step"] / (adj["ms_per_adjoint_step"] / 1e3) / 1e9 / HBM_PEAK_GBS
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -704,6 +757,7 @@ def main():
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--counters-out", default=COUNTERS,
                     help="where --summarize-counters writes (the bench line reads profiles/collide_counters.json)")
+    ap.add_argument("--summarize-adjoint-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     ap.add_argument("--adjoint-only", action="store_true", help="time only the adjoint leg, print its JSON")
     ap.add_argument("--adjoint-steps", type=int, default=20)
     ap.add_argument("--adjoint-form", default="fp32", help="storage form of --collision-adjoint")
@@ -720,6 +774,9 @@ def main():
     ap.add_argument("--spinodal-stats", nargs=2, type=int, metavar=("STEPS", "CHECK_EVERY"),
                     help="256^3 spinodal in every storage form side by side: error onset and end statistics")
     args = ap.parse_args()
+    if args.summarize_adjoint_counters:
+        summarize_adjoint_counters(*args.summarize_adjoint_counters, out_path=ADJ_COUNTERS)
+        return
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters, form=args.forms.split(",")[0], workload_name=args.workload,
                            out_path=args.counters_out)
@@ -755,7 +812,11 @@ def main():
               flush=True)
         return
     if args.adjoint_only:
-        print(json.dumps(time_adjoint(lbfe, torch, steps=args.adjoint_steps)), flush=True)
+        if args.copy_calib:
+            copy_calibration(torch)
+        adj = time_adjoint(lbfe, torch, steps=args.adjoint_steps)
+        adjoint_achieved(adj)
+        print(json.dumps(adj), flush=True)
         return
     geom, rho, u, desc = workload(args.workload, lbfe, torch)
     if args.copy_calib:
@@ -800,6 +861,7 @@ def main():
     if not args.no_adjoint:
         print("[bench] timing the adjoint (wetting workload, FP32)", file=sys.stderr, flush=True)
         adj = time_adjoint(lbfe, torch, steps=args.adjoint_steps)
+        adjoint_achieved(adj)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a bounded sample", file=sys.stderr, flush=True)

@@ -57,3 +57,33 @@ def test_counter_calibration_needs_the_copy(tmp_path):
     with pytest.raises(SystemExit):
         bench.summarize_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), "fp64", "moving",
                                  str(tmp_path / "c.json"))
+
+
+def test_adjoint_counter_summary(tmp_path):
+    """Bytes per adjoint step: every adjoint-step dispatch, calibrated by the
+    1 GiB copy, over the number of collision-adjoint dispatches; the seed and
+    the forward kernels of the run are left out."""
+    gib_kib = (1 << 30) / 1024.0
+    copy = "__amd_rocclr_copyBuffer"
+    k_c, k_p, k_r = "k_adj_collide<1, true, false>", "k_adj_phi<1, false>", "k_adj_wall_gather"
+    fetch = [(copy, gib_kib / 2), (k_c, 100.0), (k_c, 120.0), (k_p, 40.0), (k_p, 40.0),
+             (k_r, 1.0), (k_r, 1.0), (k_r, 1.0), (k_r, 1.0), ("k_adj_seed<1>", 1e6), ("k_collide<1>", 1e6)]
+    write = [(copy, gib_kib), (k_c, 50.0), (k_c, 50.0), (k_p, 10.0), (k_p, 10.0),
+             (k_r, 2.0), (k_r, 2.0), (k_r, 2.0), (k_r, 2.0), ("k_adj_seed<1>", 1e6)]
+    _counter_csv(tmp_path / "f.csv", "FETCH_SIZE", fetch)
+    _counter_csv(tmp_path / "w.csv", "WRITE_SIZE", write)
+    out = tmp_path / "a.json"
+    bench.summarize_adjoint_counters(str(tmp_path / "f.csv"), str(tmp_path / "w.csv"), str(out))
+    c = json.load(open(out))
+    assert c["adjoint_steps"] == 2
+    per_step_kib = ((100 + 120 + 40 + 40 + 4 * 1.0) * 2.0 + (50 + 50 + 10 + 10 + 4 * 2.0)) / 2
+    assert c["bytes_per_adjoint_step"] == pytest.approx(per_step_kib * 1024.0)
+    assert c["kernels_bytes_per_step"]["k_adj_wall_gather"]["WRITE_SIZE"] == pytest.approx(4 * 2.0 * 1024.0 / 2)
+    assert c["source_hash"] == bench.kernel_source_hash()
+    adj = {"ms_per_adjoint_step": 0.5}
+    bench.ADJ_COUNTERS, saved = str(out), bench.ADJ_COUNTERS
+    try:
+        bench.adjoint_achieved(adj)
+    finally:
+        bench.ADJ_COUNTERS = saved
+    assert adj["achieved_frac"] == pytest.approx(per_step_kib * 1024.0 / 0.5e-3 / 1e9 / bench.HBM_PEAK_GBS)
