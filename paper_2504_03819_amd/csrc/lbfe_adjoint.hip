@@ -10,9 +10,10 @@
 //                   bounce-back slot), local collision adjoint in central-
 //                   moment space; writes the direct part of lambda(t) and
 //                   the adjoints of u, F, Q, p_m (and rho, nu via omega_1)
-//   k_adj_phi       transposed Q stencil -> adjoint of phi; back through
-//                   phi = (p_m - rho/3) u, u = (j + F/2)/rho, F = (1/3-rho) G
-//   k_adj_mu        transposed gradient stencil -> adjoint of mu (all nodes)
+//   k_adj_phimu     transposed Q stencil -> adjoint of phi; back through
+//                   phi = (p_m - rho/3) u, u = (j + F/2)/rho, F = (1/3-rho) G;
+//                   then the transposed gradient stencil -> adjoint of mu
+//                   (all nodes), in one z-march with G_bar kept in LDS
 //   k_adj_wall_mu   (walls) wall average of Eq. (36) transposed
 //   k_adj_rho       mu0'(rho) and the (symmetric) Laplacian transposed
 //   k_adj_wall_rho* (walls) limiter/window of Eqs. (37)-(38) transposed
@@ -56,16 +57,15 @@ enum : int {
     A_PMB = 9,   // p_m bar
     A_RHOB = 10, // rho bar (local part)
     A_JB = 11,   // 3 (real): j bar, rounded to the compute precision
-    A_GB = 14,   // 3: G bar (G = grad mu)
-    A_MUB = 17,  // mu bar (all nodes)
-    A_KAPC = 18, // per-node dL/dkappa contribution
-    A_NUC = 19,  // per-node dL/dnu contribution
-    A_WETC = 20, // dL/d(wet) contribution per wall node, 2 planes packed
-    A_RAVEB = 21,// rho_ave bar at solid nodes
-    A_RHOBT = 22,// rho bar total (all nodes)
-    A_MUBT = 23, // mu bar total (all nodes)
-    A_PACK = 24, // 4 planes: (rho_bar_total, j_bar) per node as 4 compute-precision values
-    A_COUNT = 28
+    A_MUB = 14,  // mu bar (all nodes; the wall and mask transposes)
+    A_KAPC = 15, // per-node dL/dkappa contribution
+    A_NUC = 16,  // per-node dL/dnu contribution
+    A_WETC = 17, // dL/d(wet) contribution per wall node, 2 planes packed
+    A_RAVEB = 18,// rho_ave bar at solid nodes
+    A_RHOBT = 19,// rho bar total (all nodes)
+    A_MUBT = 20, // mu bar total (all nodes)
+    A_PACK = 21, // 4 planes: (rho_bar_total, j_bar) per node as 4 compute-precision values
+    A_COUNT = 25
 };
 
 // Adjoint (lambda) storage: same row-blocked layout as the populations, in
@@ -466,76 +466,136 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     A[A_NUC * N + n] = nub;
 }
 
-// phi_bar_a = transpose of Q_a = -9 sum_i w_i c_ia phi_a(x + c_i)
-// = 9 sum_i w_i c_ia Q_bar_a(x + c_i), then back through
-// phi = (p_m - rho/3) u, u = (j + F/2)/rho, F = (1/3 - rho) G, at fluid nodes.
-template <int P, bool MASK> __global__ __launch_bounds__(ZCB) void k_adj_phi(KP kp, Bufs b, int cz) {
+// The transposed Q and gradient stencils in one z-march:
+//   phi part, at fluid nodes: phi_bar_a = transpose of Q_a = -9 sum_i w_i
+//     c_ia phi_a(x + c_i) = 9 sum_i w_i c_ia Q_bar_a(x + c_i), then back
+//     through phi = (p_m - rho/3) u, u = (j + F/2)/rho, F = (1/3 - rho) G:
+//     j_bar, rho_bar (local part), G_bar and the local part of mu_bar;
+//   mu part, at every node: mu_bar(y) = local part (fluid) - 3 sum_i w_i
+//     c_i . G_bar(y + c_i) (G_bar is zero at solid nodes), into A_MUBT.
+// A workgroup owns a 32 x 16 tile of mu_bar planes [zs, ze).  Iteration k
+// evaluates the phi part at plane k+1 on the tile and its one-node ring (Q_bar
+// and mu staged with a two-node halo in a three-plane LDS ring), which leaves
+// G_bar of those 34 x 18 nodes in a three-plane LDS ring, then sums mu_bar of
+// plane k on the tile.  G_bar never goes to HBM; the owned node's j_bar and
+// rho_bar do, the ring nodes only give G_bar.
+constexpr int PWX = ZTX + 4, PNR = PWX * (ZTY + 4);  // Q_bar and mu region: tile + 2-node halo
+constexpr int GWX = ZTX + 2, GNR = GWX * (ZTY + 2);  // G_bar region: tile + 1-node ring
+constexpr int PCB = ZCB + 128;                       // threads: the tile's nodes, then the ring's
+constexpr int PPT = (PNR + PCB - 1) / PCB;           // Q_bar / mu region points per thread
+static_assert(GNR <= PCB, "one G_bar node per thread");
+
+__device__ inline int zslot3(int p) { return ((p % 3) + 3) % 3; }
+
+template <int P, bool MASK> __global__ __launch_bounds__(PCB) void k_adj_phimu(KP kp, Bufs b, int cz) {
     using real = real_t<P>;
-    __shared__ double lds[4][4][ZNR];
+    __shared__ double sq[3][4][PNR];  // Q_bar x, y, z and mu of planes p (slot p mod 3)
+    __shared__ double sg[3][3][GNR];  // G_bar of planes p (slot p mod 3)
     int x0, y0, zs, ze;
-    ztile(kp, cz, kp.z0, kp.z1, x0, y0, zs, ze);
+    ztile(kp, cz, 0, kp.nz, x0, y0, zs, ze);
     const size_t N = kp.N;
+    const unsigned plane = kp.plane;
     double *A = (double *)b.abuf;
-    ZRing<4> R;
-    R.init(kp, lds, x0, y0);
-    for (int c = 0; c < 3; ++c) {
-        if constexpr (std::is_same_v<real, float>) {
-            R.srcf[c] = aplane<float>(A, A_QB, c, N);
-            R.fmask |= 1u << c;
-        } else {
-            R.src[c] = aplane<double>(A, A_QB, c, N);
-        }
-    }
-    R.src[3] = b.mu;
     const real *j = (const real *)b.j, *F = (const real *)b.F;
-    R.march(zs, ze, [&](int k) {
-        if (!R.own) return;
+    const real *qb[3] = {aplane<real>(A, A_QB, 0, N), aplane<real>(A, A_QB, 1, N), aplane<real>(A, A_QB, 2, N)};
+    const int tid = threadIdx.x;
+    const int ta = tid % ZTX, tb = tid / ZTX;  // the tile node of threads below ZCB
+    const bool own = tid < ZCB && x0 + ta < kp.nx && y0 + tb < kp.ny;
+
+    // Q_bar / mu region points of this thread, in-plane node index
+    unsigned qoff[PPT];
+    bool qhas[PPT];
+#pragma unroll
+    for (int m = 0; m < PPT; ++m) {
+        const int r = tid + m * PCB;
+        qhas[m] = r < PNR;
+        const int rr = qhas[m] ? r : 0;
+        qoff[m] = (unsigned)zwrap(y0 + rr / PWX - 2, kp.ny) * kp.nx + zwrap(x0 + rr % PWX - 2, kp.nx);
+    }
+    double qpre[4][PPT];
+    auto load = [&](int p) {
+        const size_t base = (size_t)zwrap(p, kp.nz) * plane;
+#pragma unroll
+        for (int m = 0; m < PPT; ++m)
+            if (qhas[m]) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) qpre[c][m] = (double)qb[c][base + qoff[m]];
+                qpre[3][m] = b.mu[base + qoff[m]];
+            }
+    };
+    auto commit = [&](int p) {
+        const int sl = zslot3(p);
+#pragma unroll
+        for (int m = 0; m < PPT; ++m)
+            if (qhas[m]) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f) sq[sl][f][tid + m * PCB] = qpre[f][m];
+            }
+    };
+
+    // the phi part at plane p for G-region node (ga, gb): G_bar into LDS;
+    // for an owned node of a plane of this chunk also j_bar and rho_bar to
+    // HBM (the fill planes at both ends belong to the neighbouring chunks),
+    // and the local part of mu_bar returned
+    auto phi_node = [&](int p, int ga, int gb, bool owned) -> double {
+        const int zz = zwrap(p, kp.nz);
+        const int sm = zslot3(p - 1), s0 = zslot3(p), sp = zslot3(p + 1);
+        const int g = gb * GWX + ga;
+        const int cq = (gb + 1) * PWX + ga + 1;  // the node in the Q_bar / mu region
+        auto at = [&](int f, int dz, int dx, int dy) {
+            return sq[dz < 0 ? sm : (dz > 0 ? sp : s0)][f][cq + dy * PWX + dx];
+        };
+        const size_t n = (size_t)zz * plane + (unsigned)zwrap(y0 + gb - 1, kp.ny) * kp.nx +
+                         (unsigned)zwrap(x0 + ga - 1, kp.nx);
+        bool fl = zz >= kp.z0 && zz < kp.z1;
+        if constexpr (MASK) fl = fl && !(b.nbr[n] & kSelfBit);
+        if (!fl) {  // solid: no G_bar, no local mu_bar, nothing stored
+            sg[s0][0][g] = sg[s0][1][g] = sg[s0][2][g] = 0.0;
+            return 0.0;
+        }
         double px = 0, py = 0, pz = 0;
 #pragma unroll
         for (int a = -1; a <= 1; ++a)
 #pragma unroll
             for (int c = -1; c <= 1; ++c) {
                 const double w = w1(a) * w1(c) / 6.0;
-                px += w * (R.at(0, k + c, 1, a) - R.at(0, k + c, -1, a));
-                py += w * (R.at(1, k + c, a, 1) - R.at(1, k + c, a, -1));
-                pz += w * (R.at(2, k + 1, a, c) - R.at(2, k - 1, a, c));
+                px += w * (at(0, c, 1, a) - at(0, c, -1, a));
+                py += w * (at(1, c, a, 1) - at(1, c, a, -1));
+                pz += w * (at(2, 1, a, c) - at(2, -1, a, c));
             }
         px *= 9.0;
         py *= 9.0;
         pz *= 9.0;
-        const size_t n = (size_t)k * kp.plane + R.node;
-        if constexpr (MASK) {
-            if (b.nbr[n] & kSelfBit) return;  // solid: its source adjoints stay zero
-        }
-        // forward quantities at x, rounded as the chain kernel rounds them:
-        // u = (j + F/2) (1/rho), phi = c2 u with c2 = p_m - rho/3
-        const double r = b.rho[n], mu = R.at(3, k, 0, 0);
+        const double r = b.rho[n], mu = at(3, 0, 0, 0);
         const real ir = (real)1 / (real)r;
         const double ux = (double)((j[n] + (real)0.5 * F[n]) * ir);
         const double uy = (double)((j[N + n] + (real)0.5 * F[N + n]) * ir);
         const double uz = (double)((j[2 * N + n] + (real)0.5 * F[2 * N + n]) * ir);
         const double c2 = (double)(real)((1.0 + mu - r) * (1.0 / 3.0));
-        double pmb = A[A_PMB * N + n], rhob = A[A_RHOB * N + n];
         const double pu = px * ux + py * uy + pz * uz;
-        pmb += pu;
-        rhob -= pu / 3.0;
         const double utx = (double)aplane<real>(A, A_UB, 0, N)[n] + c2 * px;
         const double uty = (double)aplane<real>(A, A_UB, 1, N)[n] + c2 * py;
         const double utz = (double)aplane<real>(A, A_UB, 2, N)[n] + c2 * pz;
-        // u = (j + F/2)/rho; j_bar is only used in the compute precision
-        aplane<real>(A, A_JB, 0, N)[n] = (real)(utx / r);
-        aplane<real>(A, A_JB, 1, N)[n] = (real)(uty / r);
-        aplane<real>(A, A_JB, 2, N)[n] = (real)(utz / r);
         const double Fbx = (double)aplane<real>(A, A_FB, 0, N)[n] + 0.5 * utx / r;
         const double Fby = (double)aplane<real>(A, A_FB, 1, N)[n] + 0.5 * uty / r;
         const double Fbz = (double)aplane<real>(A, A_FB, 2, N)[n] + 0.5 * utz / r;
+        const double c1 = 1.0 / 3.0 - r;
+        sg[s0][0][g] = c1 * Fbx;
+        sg[s0][1][g] = c1 * Fby;
+        sg[s0][2][g] = c1 * Fbz;
+        if (!owned) return 0.0;
+        double pmb = A[A_PMB * N + n], rhob = A[A_RHOB * N + n];
+        pmb += pu;
+        rhob -= pu / 3.0;
+        aplane<real>(A, A_JB, 0, N)[n] = (real)(utx / r);
+        aplane<real>(A, A_JB, 1, N)[n] = (real)(uty / r);
+        aplane<real>(A, A_JB, 2, N)[n] = (real)(utz / r);
         rhob -= (utx * ux + uty * uy + utz * uz) / r;
-        // F = (1/3 - rho) G, G = grad_h mu recomputed
         double gx = 0.0, gy = 0.0, gz = 0.0;
 #pragma unroll
         for (int i = 0; i < 27; ++i) {
             if (i == kRest) continue;
-            const double m = wi(i) * R.at(3, k + czi(i), cxi(i), cyi(i));
+            const double m = wi(i) * at(3, czi(i), cxi(i), cyi(i));
             if (cxi(i)) gx += cxi(i) * m;
             if (cyi(i)) gy += cyi(i) * m;
             if (czi(i)) gz += czi(i) * m;
@@ -543,44 +603,64 @@ template <int P, bool MASK> __global__ __launch_bounds__(ZCB) void k_adj_phi(KP 
         gx *= 3.0;
         gy *= 3.0;
         gz *= 3.0;
-        const double c1 = 1.0 / 3.0 - r;
-        A[A_GB * N + n] = c1 * Fbx;
-        A[(A_GB + 1) * N + n] = c1 * Fby;
-        A[(A_GB + 2) * N + n] = c1 * Fbz;
         rhob -= Fbx * gx + Fby * gy + Fbz * gz;
         A[A_RHOB * N + n] = rhob;
-        A[A_MUB * N + n] = pmb / 3.0;  // local part of mu_bar (p_m = (1 + mu)/3)
-    });
-}
-
-// mu_bar(y) = local part (fluid) - 3 sum_i w_i c_i . G_bar(y + c_i), at every
-// node (G_bar is zero at solid nodes), into A_MUBT.
-__global__ __launch_bounds__(ZCB) void k_adj_mu(KP kp, Bufs b, int cz) {
-    __shared__ double lds[4][3][ZNR];
-    int x0, y0, zs, ze;
-    ztile(kp, cz, 0, kp.nz, x0, y0, zs, ze);
-    const size_t N = kp.N;
-    double *A = (double *)b.abuf;
-    ZRing<3> R;
-    R.init(kp, lds, x0, y0);
-    for (int c = 0; c < 3; ++c) R.src[c] = A + (A_GB + c) * N;
-    R.march(zs, ze, [&](int k) {
-        if (!R.own) return;
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < 27; ++i) {
-            if (i == kRest) continue;
-            const int p = k + czi(i);
-            double d = 0.0;
-            if (cxi(i)) d += cxi(i) * R.at(0, p, cxi(i), cyi(i));
-            if (cyi(i)) d += cyi(i) * R.at(1, p, cxi(i), cyi(i));
-            if (czi(i)) d += czi(i) * R.at(2, p, cxi(i), cyi(i));
-            s += wi(i) * d;
+        return pmb / 3.0;  // p_m = (1 + mu)/3
+    };
+    // ring-only G-region node q of thread ZCB + q
+    auto ring_node = [&](int q, int &ga, int &gb) {
+        if (q < GWX) {
+            ga = q, gb = 0;
+        } else if (q < 2 * GWX) {
+            ga = q - GWX, gb = ZTY + 1;
+        } else if (q < 2 * GWX + ZTY) {
+            ga = 0, gb = q - 2 * GWX + 1;
+        } else {
+            ga = GWX - 1, gb = q - 2 * GWX - ZTY + 1;
         }
-        const size_t n = (size_t)k * kp.plane + R.node;
-        const bool fluid = k >= kp.z0 && k < kp.z1;
-        A[A_MUBT * N + n] = (fluid ? A[A_MUB * N + n] : 0.0) - 3.0 * s;
-    });
+    };
+
+    double mloc_k = 0.0;  // local mu_bar of the owned node, plane k
+    load(zs - 2);
+    commit(zs - 2);
+    load(zs - 1);
+    commit(zs - 1);
+    load(zs);
+    for (int k = zs - 2; k < ze; ++k) {
+        commit(k + 2);
+        __syncthreads();
+        if (k + 3 <= ze + 1) load(k + 3);
+        // phi part at plane k+1: the tile's nodes and the ring's, one per thread
+        double mloc_next = 0.0;
+        if (tid < ZCB) {
+            mloc_next = phi_node(k + 1, ta + 1, tb + 1, own && k + 1 >= zs && k + 1 < ze);
+        } else if (tid < GNR) {
+            int ga, gb;
+            ring_node(tid - ZCB, ga, gb);
+            phi_node(k + 1, ga, gb, false);
+        }
+        __syncthreads();
+        if (k >= zs && own) {
+            const int sm = zslot3(k - 1), s0 = zslot3(k), sp = zslot3(k + 1);
+            const int g = (tb + 1) * GWX + ta + 1;
+            double sum = 0.0;
+#pragma unroll
+            for (int i = 0; i < 27; ++i) {
+                if (i == kRest) continue;
+                const int sl = czi(i) < 0 ? sm : (czi(i) > 0 ? sp : s0);
+                const int gi = g + cyi(i) * GWX + cxi(i);
+                double d = 0.0;
+                if (cxi(i)) d += cxi(i) * sg[sl][0][gi];
+                if (cyi(i)) d += cyi(i) * sg[sl][1][gi];
+                if (czi(i)) d += czi(i) * sg[sl][2][gi];
+                sum += wi(i) * d;
+            }
+            const size_t n = (size_t)k * plane + (unsigned)(y0 + tb) * kp.nx + (x0 + ta);
+            const bool fluid = k >= kp.z0 && k < kp.z1;
+            A[A_MUBT * N + n] = (fluid ? mloc_k : 0.0) - 3.0 * sum;
+        }
+        mloc_k = mloc_next;
+    }
 }
 
 // Normalising weight sum of the wall average at solid node (x, y, zs).
@@ -943,19 +1023,16 @@ template <class Fn> hipError_t dispatch(int prec, Fn &&fn) {
 
 constexpr unsigned kReduceBlocks = 1024;  // blocks of the gradient reduction
 
-// The chain from mu_bar (local parts already in A_MUB, G_bar in A_GB) to
-// rho_bar_total (A_RHOBT) with walls, and the kappa / wet accumulation.
+// The chain from mu_bar (A_MUBT after k_adj_phimu; in the initialiser's
+// adjoint its local part in A_MUB) to rho_bar_total (A_RHOBT) with walls,
+// and the kappa / wet accumulation.
 hipError_t chain_tail(hipStream_t s, const KP &kp, const Bufs &b, bool with_gradient_transpose,
                       const double *nuc) {
     const size_t N = kp.N;
     double *A = (double *)b.abuf;
     const unsigned gN = nblocks(N), gw = nblocks(2 * (size_t)kp.plane);
-    double *mub_tot = A + A_MUB * N;
+    double *mub_tot = A + (with_gradient_transpose ? A_MUBT : A_MUB) * N;
     const dim3 gall = zgrid(kp, 0, kp.nz);
-    if (with_gradient_transpose) {
-        k_adj_mu<<<gall, ZCB, 0, s>>>(kp, b, kZChunk);
-        mub_tot = A + A_MUBT * N;
-    }
     const double *wetc = nullptr;
     unsigned nwet = 0;
     if (kp.masked) {
@@ -1043,13 +1120,13 @@ hipError_t launch_adj_step(hipStream_t s, int prec, const KP &kp, const Bufs &b,
                 k_adj_collide<P, true, true><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
             else
                 k_adj_collide<P, false, true><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
-            k_adj_phi<P, true><<<zgrid(kp, kp.z0, kp.z1), ZCB, 0, s>>>(kp, b, kZChunk);
+            k_adj_phimu<P, true><<<zgrid(kp, 0, kp.nz), PCB, 0, s>>>(kp, b, kZChunk);
         } else {
             if (pending)
                 k_adj_collide<P, true, false><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
             else
                 k_adj_collide<P, false, false><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
-            k_adj_phi<P, false><<<zgrid(kp, kp.z0, kp.z1), ZCB, 0, s>>>(kp, b, kZChunk);
+            k_adj_phimu<P, false><<<zgrid(kp, 0, kp.nz), PCB, 0, s>>>(kp, b, kZChunk);
         }
         hipError_t r = chain_tail(s, kp, b, true, A + A_NUC * (size_t)kp.N);
         if (r != hipSuccess) return r;

@@ -65,7 +65,7 @@ def test_adjoint_counter_summary(tmp_path):
     the forward kernels of the run are left out."""
     gib_kib = (1 << 30) / 1024.0
     copy = "__amd_rocclr_copyBuffer"
-    k_c, k_p, k_r = "k_adj_collide<1, true, false>", "k_adj_phi<1, false>", "k_adj_wall_gather"
+    k_c, k_p, k_r = "k_adj_collide<1, true, false>", "k_adj_phimu<1, false>", "k_adj_wall_gather"
     fetch = [(copy, gib_kib / 2), (k_c, 100.0), (k_c, 120.0), (k_p, 40.0), (k_p, 40.0),
              (k_r, 1.0), (k_r, 1.0), (k_r, 1.0), (k_r, 1.0), ("k_adj_seed<1>", 1e6), ("k_collide<1>", 1e6)]
     write = [(copy, gib_kib), (k_c, 50.0), (k_c, 50.0), (k_p, 10.0), (k_p, 10.0),
