@@ -402,27 +402,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
             }
         }
     }
-    // moving walls: a reflected population carries -[f^eq_i - f^eq_opp(i)](rho,
-    // p_m, u_w) (k_wall_move), which is linear in (rho, p_m) at a given u_w;
-    // its adjoint adds to the node's rho_bar and p_m_bar
-    double wrb = 0.0, wpb = 0.0;
-    if (kp.moving && (wall_lo || wall_hi)) {
-        for (int w = 0; w < 2; ++w) {
-            if (!(w == 0 ? wall_lo : wall_hi)) continue;
-            real ea[27], eb[27];
-            const real uwx = (real)kp.wall_u[2 * w], uwy = (real)kp.wall_u[2 * w + 1];
-            wall_equilibrium((real)1, (real)0, uwx, uwy, ea);
-            wall_equilibrium((real)0, (real)1, uwx, uwy, eb);
-#pragma unroll
-            for (int i = 0; i < 27; ++i) {
-                const int cz = czi(i);
-                if ((w == 0 && cz < 0) || (w == 1 && cz > 0)) {
-                    wrb -= (double)l[i] * (double)(ea[i] - ea[26 - i]);
-                    wpb -= (double)l[i] * (double)(eb[i] - eb[26 - i]);
-                }
-            }
-        }
-    }
+    // (moving walls: the wall term's adjoint is added by k_adj_wall_move)
     cm_inverse_T(l, ux, uy, uz);  // l = lambda_hat (adjoint of k*)
     real ubx, uby, ubz;
     shift_dot(l, ks, ubx, uby, ubz);  // lambda_hat . S k*
@@ -447,8 +427,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     // omega_1 = 1 / (rho nu / p_m + 1/2)
     const double o = (double)om1, dpm = (double)pm, rr = rd;
     const double om1b = (double)sb.om1;
-    const double rhob = -om1b * o * o * kp.nu / dpm + wrb;
-    const double pmb = (double)sb.pm + om1b * o * o * rr * kp.nu / (dpm * dpm) + wpb;
+    const double rhob = -om1b * o * o * kp.nu / dpm;
+    const double pmb = (double)sb.pm + om1b * o * o * rr * kp.nu / (dpm * dpm);
     const double nub = -om1b * o * o * rr / dpm;
     const size_t N = kp.N;
     double *A = (double *)b.abuf;
@@ -464,6 +444,53 @@ __global__ __launch_bounds__(kBlock) void k_adj_collide(KP kp, Bufs b, const voi
     A[A_PMB * N + n] = pmb;
     A[A_RHOB * N + n] = rhob;
     A[A_NUC * N + n] = nub;
+}
+
+// Moving walls: a reflected population carries -[f^eq_i - f^eq_opp(i)](rho,
+// p_m, u_w) (k_wall_move), which is linear in (rho, p_m) at a given u_w; its
+// adjoint adds to rho_bar and p_m_bar of the wall-adjacent nodes, from the
+// lambda* that k_adj_collide gathered on the reflected links (a kernel of its
+// own, after k_adj_collide: the wall equilibria would raise the collision
+// adjoint's register count past two waves per SIMD in FP64).
+template <int P, bool PEND>
+__global__ __launch_bounds__(kBlock) void k_adj_wall_move(KP kp, Bufs b, const void *lam_in) {
+    using real = real_t<P>;
+    const unsigned idx = blockIdx.x * kBlock + threadIdx.x;
+    if (idx >= 2 * kp.plane) return;
+    const int side = idx >= kp.plane;
+    if (side && kp.nz - 2 == 1) return;  // one fluid plane: both walls by side 0
+    const unsigned p = idx - (side ? kp.plane : 0u);
+    const int y = (int)(p / (unsigned)kp.nx), x = (int)(p - (unsigned)y * kp.nx);
+    const int z = side ? kp.nz - 2 : 1;
+    const size_t n = (size_t)z * kp.plane + p;
+    const Nb nb(kp, x, y, z);
+    const unsigned row = nb.row(0, 0);
+    const Lam<real> lin(const_cast<void *>(lam_in), kp);
+    const Pack4<real> *pk = (const Pack4<real> *)((const double *)b.abuf + A_PACK * (size_t)kp.N);
+    const bool wall_lo = z == 1, wall_hi = z == kp.nz - 2;
+    double wrb = 0.0, wpb = 0.0;
+    for (int w = 0; w < 2; ++w) {
+        if (!(w == 0 ? wall_lo : wall_hi)) continue;
+        real ea[27], eb[27];
+        const real uwx = (real)kp.wall_u[2 * w], uwy = (real)kp.wall_u[2 * w + 1];
+        wall_equilibrium((real)1, (real)0, uwx, uwy, ea);
+        wall_equilibrium((real)0, (real)1, uwx, uwy, eb);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const int cz = czi(i);
+            if ((w == 0 && cz < 0) || (w == 1 && cz > 0)) {
+                // lambda*_i at a reflected link: the node's own value of the
+                // opposite direction, plus its pending last term
+                real li = lin.ld(26 - i, row, (unsigned)x);
+                if constexpr (PEND) li = li + final_term<real>(pk, 26 - i, n);
+                wrb -= (double)li * (double)(ea[i] - ea[26 - i]);
+                wpb -= (double)li * (double)(eb[i] - eb[26 - i]);
+            }
+        }
+    }
+    double *A = (double *)b.abuf;
+    A[A_RHOB * kp.N + n] += wrb;
+    A[A_PMB * kp.N + n] += wpb;
 }
 
 // The transposed Q and gradient stencils in one z-march:
@@ -576,9 +603,12 @@ template <int P, bool MASK> __global__ __launch_bounds__(PCB) void k_adj_phimu(K
         const double utx = (double)aplane<real>(A, A_UB, 0, N)[n] + c2 * px;
         const double uty = (double)aplane<real>(A, A_UB, 1, N)[n] + c2 * py;
         const double utz = (double)aplane<real>(A, A_UB, 2, N)[n] + c2 * pz;
-        const double Fbx = (double)aplane<real>(A, A_FB, 0, N)[n] + 0.5 * utx / r;
-        const double Fby = (double)aplane<real>(A, A_FB, 1, N)[n] + 0.5 * uty / r;
-        const double Fbz = (double)aplane<real>(A, A_FB, 2, N)[n] + 0.5 * utz / r;
+        // u = (j + F/2)/rho: j_bar = u_tilde/rho, F_bar += j_bar/2 (halving
+        // the quotient rounds as dividing the halved numerator does)
+        const double jbx = utx / r, jby = uty / r, jbz = utz / r;
+        const double Fbx = (double)aplane<real>(A, A_FB, 0, N)[n] + 0.5 * jbx;
+        const double Fby = (double)aplane<real>(A, A_FB, 1, N)[n] + 0.5 * jby;
+        const double Fbz = (double)aplane<real>(A, A_FB, 2, N)[n] + 0.5 * jbz;
         const double c1 = 1.0 / 3.0 - r;
         sg[s0][0][g] = c1 * Fbx;
         sg[s0][1][g] = c1 * Fby;
@@ -587,9 +617,9 @@ template <int P, bool MASK> __global__ __launch_bounds__(PCB) void k_adj_phimu(K
         double pmb = A[A_PMB * N + n], rhob = A[A_RHOB * N + n];
         pmb += pu;
         rhob -= pu / 3.0;
-        aplane<real>(A, A_JB, 0, N)[n] = (real)(utx / r);
-        aplane<real>(A, A_JB, 1, N)[n] = (real)(uty / r);
-        aplane<real>(A, A_JB, 2, N)[n] = (real)(utz / r);
+        aplane<real>(A, A_JB, 0, N)[n] = (real)jbx;
+        aplane<real>(A, A_JB, 1, N)[n] = (real)jby;
+        aplane<real>(A, A_JB, 2, N)[n] = (real)jbz;
         rhob -= (utx * ux + uty * uy + utz * uz) / r;
         double gx = 0.0, gy = 0.0, gz = 0.0;
 #pragma unroll
@@ -1126,6 +1156,13 @@ hipError_t launch_adj_step(hipStream_t s, int prec, const KP &kp, const Bufs &b,
                 k_adj_collide<P, true, false><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
             else
                 k_adj_collide<P, false, false><<<gf, kBlock, 0, s>>>(kp, b, ft, b.lam[lcur], b.lam[1 - lcur]);
+            if (kp.moving) {
+                const unsigned gw = nblocks(2 * (size_t)kp.plane);
+                if (pending)
+                    k_adj_wall_move<P, true><<<gw, kBlock, 0, s>>>(kp, b, b.lam[lcur]);
+                else
+                    k_adj_wall_move<P, false><<<gw, kBlock, 0, s>>>(kp, b, b.lam[lcur]);
+            }
             k_adj_phimu<P, false><<<zgrid(kp, 0, kp.nz), PCB, 0, s>>>(kp, b, kZChunk);
         }
         hipError_t r = chain_tail(s, kp, b, true, A + A_NUC * (size_t)kp.N);
