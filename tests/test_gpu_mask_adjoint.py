@@ -55,6 +55,7 @@ CASES = [
     ("pillars phi 1.3 ragged", "pillars", (14, 19, 21), dict(wet_mode=1, wet_value=1.3)),
     ("planes drho 1.2", "planes", (9, 8, 11), dict(wet_mode=2, wet_value=1.2)),
     ("obstacles 70 wide, several tiles", "obstacles", (8, 6, 70), dict(wet_mode=1, wet_value=1.6)),
+    ("pillars drho 0.9, three z-chunks", "pillars", (36, 9, 11), dict(wet_mode=2, wet_value=0.9)),
 ]
 
 
