@@ -76,8 +76,7 @@ STEP_KERNELS = ("k_moments", "k_chain", "k_collide", "k_fused", "k_wall_rho", "k
 ADJ_COUNTERS = os.path.join(ROOT, "profiles", "adjoint_counters.json")
 # kernels of one adjoint step with the forward fields kept (the seed, the
 # read-out and the initialiser's adjoint are not part of a step)
-ADJ_STEP_KERNELS = ("k_adj_collide", "k_adj_phi", "k_adj_mu", "k_adj_rho", "k_adj_wall", "k_adj_pack",
-                    "k_adj_reduce")
+ADJ_STEP_KERNELS = ("k_adj_collide", "k_adj_phimu", "k_adj_rho", "k_adj_wall", "k_adj_pack", "k_adj_reduce")
 PATH_NAMES = {1: "two-pass", 2: "fused", 3: "state"}
 DOMINANT = {"two-pass": "k_collide (collide + push-stream)",
             "fused": "k_fused (collide + stream + next-step moments)",

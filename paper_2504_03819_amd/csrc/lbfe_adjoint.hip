@@ -10,13 +10,17 @@
 //                   bounce-back slot), local collision adjoint in central-
 //                   moment space; writes the direct part of lambda(t) and
 //                   the adjoints of u, F, Q, p_m (and rho, nu via omega_1)
+//   k_adj_wall_move (moving walls) the wall-velocity term of the reflected
+//                   populations transposed into rho_bar and p_m_bar
 //   k_adj_phimu     transposed Q stencil -> adjoint of phi; back through
 //                   phi = (p_m - rho/3) u, u = (j + F/2)/rho, F = (1/3-rho) G;
 //                   then the transposed gradient stencil -> adjoint of mu
 //                   (all nodes), in one z-march with G_bar kept in LDS
-//   k_adj_wall_mu   (walls) wall average of Eq. (36) transposed
+//   k_adj_wall_gather (walls) wall average of Eq. (36) transposed
 //   k_adj_rho       mu0'(rho) and the (symmetric) Laplacian transposed
-//   k_adj_wall_rho* (walls) limiter/window of Eqs. (37)-(38) transposed
+//   k_adj_wall_rho_solid, k_adj_wall_gather (walls) limiter/window of
+//                   Eqs. (37)-(38) transposed
+//   k_adj_pack      (rho_bar_total, j_bar) per node, for the next step's gather
 //   k_adj_final     lambda_i(t) += rho_bar + c_i . j_bar, applied when lambda
 //                   is read out; between adjoint steps this term is added by
 //                   the next step's gather instead
@@ -25,8 +29,8 @@
 // from the neighbour words, solid nodes hold no lambda and no source
 // adjoints, and the wall averages and window of every solid node are
 // transposed per node (k_adj_wall_gather_m, k_adj_wall_rho_solid_m).  With
-// moving walls the collision adjoint also transposes the wall-velocity term
-// of the reflected populations.
+// moving walls k_adj_wall_move transposes the wall-velocity term of the
+// reflected populations.
 #include <type_traits>
 
 #include "lbfe_device.h"
