@@ -353,3 +353,47 @@ def test_dot_product_of_one_step(walls):
     rel = abs(a - b) / abs(b)
     say(f"dot-product test walls={walls}: <Jv,w> = {a:.12e}, <v,J^T w> = {b:.12e}, rel {rel:.1e}")
     assert rel < 1e-8
+
+
+def test_dot_product_of_one_step_full_size():
+    """The dot-product test on the full 192x192x96 sessile-droplet workload
+    (walls z = 0 and 95, r = 32, 0.7 T_c, omega_3 = 1/2, FP64): 72 tiles and
+    six z-chunks of the transposed-stencil march, the tile order and chunk
+    lengths that the adjoint benchmark runs.  Neutral wetting (no window of
+    Eq. (38), so no branch for the difference quotient to straddle).  J v by
+    central differences of the GPU forward step, J^T w by one adjoint step;
+    every tensor stays on the device.  The rounding of the difference
+    quotient, about 1e-16 |f| / (h |v|) per term with random signs, keeps
+    the relative gap near 1e-9 at any size; the bound is 1e-8 as for the
+    small boxes."""
+    nx, ny, nz = 192, 192, 96
+    shape = (nz, ny, nx)
+    T = eos.temperature(0.7)
+    sim = make_sim(nx=nx, ny=ny, nz=nz, T=T, walls_z=1, wet_mode=0, adjoint=1,
+                   omega=[1.0, 1.0, 1.0, 0.5] + [1.0] * 7)
+    rl, rv = eos.maxwell(eos.PAPER["a"], eos.PAPER["b"], eos.PAPER["R"], T)
+    sim.init_density(torch.tensor(inputs.sessile_droplet(rl, rv)[0]))
+    sim.step(20)
+    f = sim.populations()
+    gen = torch.Generator(device=f.device)
+    gen.manual_seed(43)
+    fluid = (f != 0).double()
+    v = (torch.rand(f.shape, generator=gen, device=f.device, dtype=DT) * 2 - 1) * fluid * 1e-3
+    w = (torch.rand(f.shape, generator=gen, device=f.device, dtype=DT) * 2 - 1) * fluid
+    h = 1e-3
+
+    def step_of(ff):
+        sim.set_populations(ff)
+        sim.step(1)
+        return sim.populations()
+
+    Jv = (step_of(f + h * v) - step_of(f - h * v)) / (2 * h)
+    sim.set_populations(f)
+    state = sim.get_state().clone()
+    sim.adjoint_seed_populations(w)
+    sim.adjoint_step(state)
+    JTw = sim.adjoint_state()
+    a, b = float((Jv * w).sum()), float((v * JTw).sum())
+    rel = abs(a - b) / abs(b)
+    say(f"full-size dot-product test: <Jv,w> = {a:.12e}, <v,J^T w> = {b:.12e}, rel {rel:.1e}")
+    assert rel < 1e-8
