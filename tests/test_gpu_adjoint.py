@@ -355,24 +355,42 @@ def test_dot_product_of_one_step(walls):
     assert rel < 1e-8
 
 
-def test_dot_product_of_one_step_full_size():
-    """The dot-product test on the full 192x192x96 sessile-droplet workload
-    (walls z = 0 and 95, r = 32, 0.7 T_c, omega_3 = 1/2, FP64): 72 tiles and
-    six z-chunks of the transposed-stencil march, the tile order and chunk
-    lengths that the adjoint benchmark runs.  Neutral wetting (no window of
-    Eq. (38), so no branch for the difference quotient to straddle).  J v by
-    central differences of the GPU forward step, J^T w by one adjoint step;
-    every tensor stays on the device.  The rounding of the difference
-    quotient, about 1e-16 |f| / (h |v|) per term with random signs, keeps
-    the relative gap near 1e-9 at any size; the bound is 1e-8 as for the
-    small boxes."""
-    nx, ny, nz = 192, 192, 96
-    shape = (nz, ny, nx)
+FULL = [
+    # (label, shape (nz, ny, nx), extra Simulation keywords, density builder)
+    ("sessile 192x192x96", (96, 192, 192), dict(walls_z=1),
+     lambda rl, rv: inputs.sessile_droplet(rl, rv)[0]),
+    ("pillars mask 192x192x96", (96, 192, 192), dict(),
+     lambda rl, rv: np.where(_pillars((96, 192, 192)).astype(bool), rv,
+                             inputs.sphere((96, 192, 192), (96.0, 96.0, 8.0), 32.0, rl, rv))),
+    ("moving walls 128^3", (128, 128, 128), dict(walls_z=1, wall_u=(0.1, 0.0, 0.1, 0.0)),
+     lambda rl, rv: inputs.sphere((128, 128, 128), (64, 64, 64), 30.0, rl, rv)),
+]
+
+
+def _pillars(shape):
+    return inputs.mask_pillars(shape, plate=2, pitch=12, width=4, height=6)
+
+
+@pytest.mark.parametrize("label,shape,extra,rho_of", FULL, ids=[c[0] for c in FULL])
+def test_dot_product_of_one_step_full_size(label, shape, extra, rho_of):
+    """The dot-product test on full-size workloads of the benchmark (FP64,
+    0.7 T_c, omega_3 = 1/2): the 192x192x96 sessile droplet between walls
+    and the droplet on the pillared solid mask (72 tiles and six z-chunks of
+    the transposed-stencil march), and the 128^3 droplet between moving
+    walls.  Neutral wetting (no window of Eq. (38), so no branch for the
+    difference quotient to straddle).  J v by central differences of the GPU
+    forward step, J^T w by one adjoint step; every tensor stays on the
+    device.  The rounding of the difference quotient, about
+    1e-16 |f| / (h |v|) per term with random signs, keeps the relative gap
+    near 1e-9 at any size; the bound is 1e-8 as for the small boxes."""
+    nz, ny, nx = shape
     T = eos.temperature(0.7)
-    sim = make_sim(nx=nx, ny=ny, nz=nz, T=T, walls_z=1, wet_mode=0, adjoint=1,
-                   omega=[1.0, 1.0, 1.0, 0.5] + [1.0] * 7)
+    kw = dict(extra)
+    if label.startswith("pillars"):
+        kw["solid"] = _pillars(shape)
+    sim = make_sim(nx=nx, ny=ny, nz=nz, T=T, wet_mode=0, adjoint=1, omega=[1.0, 1.0, 1.0, 0.5] + [1.0] * 7, **kw)
     rl, rv = eos.maxwell(eos.PAPER["a"], eos.PAPER["b"], eos.PAPER["R"], T)
-    sim.init_density(torch.tensor(inputs.sessile_droplet(rl, rv)[0]))
+    sim.init_density(torch.tensor(rho_of(rl, rv)))
     sim.step(20)
     f = sim.populations()
     gen = torch.Generator(device=f.device)
@@ -395,5 +413,5 @@ def test_dot_product_of_one_step_full_size():
     JTw = sim.adjoint_state()
     a, b = float((Jv * w).sum()), float((v * JTw).sum())
     rel = abs(a - b) / abs(b)
-    say(f"full-size dot-product test: <Jv,w> = {a:.12e}, <v,J^T w> = {b:.12e}, rel {rel:.1e}")
+    say(f"full-size dot-product test {label}: <Jv,w> = {a:.12e}, <v,J^T w> = {b:.12e}, rel {rel:.1e}")
     assert rel < 1e-8
