@@ -270,6 +270,31 @@ def test_full_size_collision_512_fp32_sampled():
     _sampled_windows(sim, f_t, f_t1, centres, 2e-6, "512^3 collision FP32")
 
 
+def test_full_size_collision_512_fp64_sampled():
+    """The benchmark's headline configuration: the 512^3 head-on collision
+    in FP64 on the path and schedule the library picks for it (the fused
+    collide-stream-moments kernel, XCD-contiguous tile order, 64-plane
+    chunks), 10 steps in: sampled windows against the oracle to the FP64
+    tolerance of the one-step cases."""
+    n = 512
+    T = eos.temperature(0.85)
+    sim = make_sim(nx=n, ny=n, nz=n, T=T, check_every=1000)
+    assert sim.params.step_path == lbfe.PATH_FUSED and sim.params.tile_order == lbfe.ORDER_XCD
+    rho0, u0 = inputs.head_on_collision(sim.rho_l, sim.rho_v)
+    sim.init_density(torch.tensor(rho0), torch.tensor(u0))
+    del rho0, u0
+    sim.step(10)
+    f_t = sim.populations()
+    sim.step(1)
+    f_t1 = sim.populations()
+    centres = [(256, 256, 176 + 64), (256, 256, 336 - 64), (256, 256 + 64, 176), (256, 256, 256), (0, 0, 0),
+               (300, 200, 176), (511, 511, 511), (64, 448, 100)]
+    _sampled_windows(sim, f_t, f_t1, centres, TOL, "512^3 collision FP64 (fused)")
+    del f_t, f_t1
+    sim.close()
+    torch.cuda.empty_cache()
+
+
 def test_step_is_deterministic():
     T = eos.temperature(0.8)
     sim = make_sim(nx=24, ny=20, nz=16, T=T)
