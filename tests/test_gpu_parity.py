@@ -7,7 +7,7 @@ import pytest
 import torch
 
 from gpu_util import (DT, droplet_rho, fluid_slice, gpu_fields, make_sim, oracle_fields, oracle_params, rel_err,
-                      say)
+                      sampled_windows, say)
 from oracle import eos, lbm
 from paper_2504_03819_amd import inputs, lbfe
 
@@ -155,47 +155,6 @@ def test_trajectory_moving_walls():
     assert e < TOL and all(v < TOL for v in errs.values())
 
 
-def _window_step(f_win, p_win):
-    return lbm.step(f_win, p_win)
-
-
-def _sampled_windows(sim, f_t, f_t1, centres, tol, label):
-    """Oracle steps of 17^3 windows of f(t) (device tensors, indexed on the
-    device) around the sample centres, compared on the central 5^3 with
-    f(t+1).  In the bulk a node's update depends on f(t) within 4 nodes (3
-    stencil hops plus streaming); next to a wall within 6 in x and y, since
-    the wall density and the wall chemical potential each average the first
-    fluid layer over x+-1, y+-1.  Next to a wall the window starts (ends) at
-    the real solid plane and the first (last) five fluid planes are compared;
-    the oracle also treats the window's far z-face as solid, which stays
-    more than 6 planes away."""
-    p = oracle_params(sim)
-    nz, ny, nx = sim.shape
-    worst = 0.0
-    mid = slice(6, 11)
-    for (cz, cy, cx) in centres:
-        iy = np.arange(cy - 8, cy + 9) % ny
-        ix = np.arange(cx - 8, cx + 9) % nx
-        if p.walls_z and cz < 9:
-            iz, cmp_z, walls = np.arange(0, 17), slice(1, 6), True
-        elif p.walls_z and cz > nz - 10:
-            iz, cmp_z, walls = np.arange(nz - 17, nz), slice(11, 16), True
-        else:
-            iz, cmp_z, walls = np.arange(cz - 8, cz + 9) % nz, mid, False
-        dev = f_t.device
-        tz, ty, tx = (torch.as_tensor(v, device=dev) for v in (iz, iy, ix))
-        win = f_t.index_select(1, tz).index_select(2, ty).index_select(3, tx).double().cpu()
-        pw = lbm.Params(17, 17, 17, walls_z=walls, T=p.T, kappa=p.kappa, nu=p.nu, omega=p.omega, corr4=p.corr4,
-                        rho_l=p.rho_l, rho_v=p.rho_v, wet_mode=p.wet_mode, wet_value=p.wet_value,
-                        wall_u=p.wall_u)
-        fo = _window_step(win, pw)[:, cmp_z, mid, mid]
-        fg = f_t1.index_select(1, tz[cmp_z]).index_select(2, ty[mid]).index_select(3, tx[mid]).double().cpu()
-        e = float((fg - fo).abs().max() / fo.abs().max())
-        worst = max(worst, e)
-    say(f"{label}: sampled windows, max rel err {worst:.2e}")
-    assert worst < tol
-
-
 def test_full_size_moving_droplet_sampled():
     """128^3 moving droplet (the benchmark workload), one step in the
     benchmark's launch configuration; the oracle recomputes sampled nodes
@@ -213,7 +172,7 @@ def test_full_size_moving_droplet_sampled():
     # sample centres on the interface, in the liquid and in the vapour
     centres = [tuple(int(v) for v in g.integers(0, n, 3)) for _ in range(4)]
     centres += [(64, 64, 64 + 24), (64, 64 + 24, 64), (0, 0, 0), (127, 64, 40)]
-    _sampled_windows(sim, f_t, f_t1, centres, TOL, "128^3 moving droplet")
+    sampled_windows(sim, f_t, f_t1, centres, TOL, "128^3 moving droplet")
 
 
 def test_full_size_spinodal_sampled():
@@ -230,7 +189,7 @@ def test_full_size_spinodal_sampled():
     f_t1 = sim.populations()
     g = np.random.Generator(np.random.PCG64(6))
     centres = [tuple(int(v) for v in g.integers(0, n, 3)) for _ in range(6)] + [(0, 255, 128), (255, 0, 0)]
-    _sampled_windows(sim, f_t, f_t1, centres, TOL, "256^3 spinodal")
+    sampled_windows(sim, f_t, f_t1, centres, TOL, "256^3 spinodal")
 
 
 def test_full_size_wetting_sampled():
@@ -248,7 +207,7 @@ def test_full_size_wetting_sampled():
     f_t1 = sim.populations()
     centres = [(2, 96, 96), (3, 96, 96 + 32), (1, 96 + 31, 96), (2, 0, 0), (93, 50, 60), (94, 96, 96),
                (20, 96, 96 + 28), (48, 10, 150)]
-    _sampled_windows(sim, f_t, f_t1, centres, TOL, "192x192x96 wetting")
+    sampled_windows(sim, f_t, f_t1, centres, TOL, "192x192x96 wetting")
 
 
 def test_full_size_collision_512_fp32_sampled():
@@ -267,7 +226,7 @@ def test_full_size_collision_512_fp32_sampled():
     f_t1 = sim.populations()
     centres = [(256, 256, 176 + 64), (256, 256, 336 - 64), (256, 256 + 64, 176), (256, 256, 256), (0, 0, 0),
                (300, 200, 176)]
-    _sampled_windows(sim, f_t, f_t1, centres, 2e-6, "512^3 collision FP32")
+    sampled_windows(sim, f_t, f_t1, centres, 2e-6, "512^3 collision FP32")
 
 
 def test_full_size_collision_512_fp64_sampled():
@@ -289,7 +248,7 @@ def test_full_size_collision_512_fp64_sampled():
     f_t1 = sim.populations()
     centres = [(256, 256, 176 + 64), (256, 256, 336 - 64), (256, 256 + 64, 176), (256, 256, 256), (0, 0, 0),
                (300, 200, 176), (511, 511, 511), (64, 448, 100)]
-    _sampled_windows(sim, f_t, f_t1, centres, TOL, "512^3 collision FP64 (fused)")
+    sampled_windows(sim, f_t, f_t1, centres, TOL, "512^3 collision FP64 (fused)")
     del f_t, f_t1
     sim.close()
     torch.cuda.empty_cache()

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import make_sim, say
+from gpu_util import make_sim, sampled_windows, say
 from oracle import eos
 from paper_2504_03819_amd import inputs, lbfe
 
@@ -127,7 +127,6 @@ def test_fp16_one_step_against_the_oracle(form):
 def test_fp16_full_size_spinodal_sampled(form):
     """The 256^3 spinodal workload in the FP16 forms, 20 steps in: sampled
     windows of the decoded state stepped by the FP64 oracle."""
-    from test_gpu_parity import _sampled_windows
     n = 256
     T = eos.temperature(0.8)
     sim = make_sim(nx=n, ny=n, nz=n, T=T, precision=form, check_every=1000)
@@ -139,4 +138,4 @@ def test_fp16_full_size_spinodal_sampled(form):
     f_t1 = sim.populations()
     g = np.random.Generator(np.random.PCG64(16))
     centres = [tuple(int(v) for v in g.integers(0, n, 3)) for _ in range(5)] + [(0, 0, 0)]
-    _sampled_windows(sim, f_t, f_t1, centres, ONE_STEP_TOL[form], f"256^3 spinodal {form}")
+    sampled_windows(sim, f_t, f_t1, centres, ONE_STEP_TOL[form], f"256^3 spinodal {form}")

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_util import DT, droplet_rho, make_sim, oracle_params, rel_err, say
+from gpu_util import DT, droplet_rho, make_sim, oracle_params, rel_err, sampled_windows, say
 from oracle import eos, lbm
 from paper_2504_03819_amd import inputs, lbfe
 
@@ -166,3 +166,26 @@ def test_state_path_long_run_equals_two_pass(form):
             s.step(n)
         assert torch.equal(sims[0].get_state(), sims[1].get_state()), (form, n)
     say(f"64^3 {form}: state path equals two-pass after 508 steps")
+
+
+def test_state_path_full_size_collision_sampled():
+    """The 512^3 head-on collision (the benchmark's `fp64_state` form) on the
+    state path, 10 steps in one call and one more: sampled windows of f(t)
+    stepped by the oracle against f(t+1), FP64 tolerance."""
+    n = 512
+    T = eos.temperature(0.85)
+    sim = make_sim(nx=n, ny=n, nz=n, T=T, check_every=1000, step_path=lbfe.PATH_STATE)
+    assert sim.params.step_path == lbfe.PATH_STATE
+    rl, rv = eos.maxwell(eos.PAPER["a"], eos.PAPER["b"], 1.0, T)
+    rho0, u0 = inputs.head_on_collision(rl, rv)
+    sim.init_density(torch.tensor(rho0), torch.tensor(u0))
+    del rho0, u0
+    sim.step(10)
+    f_t = sim.populations()
+    sim.step(1)
+    f_t1 = sim.populations()
+    centres = [(256, 256, 176 + 64), (256, 256, 336 - 64), (256, 256 + 64, 176), (0, 0, 0), (511, 300, 20)]
+    sampled_windows(sim, f_t, f_t1, centres, 1e-11, "512^3 collision, state path FP64")
+    del f_t, f_t1
+    sim.close()
+    torch.cuda.empty_cache()
