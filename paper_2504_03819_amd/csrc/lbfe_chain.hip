@@ -141,6 +141,21 @@ __global__ __launch_bounds__(CB) void k_chain(KP kp, const double *__restrict__ 
     auto ioff = [&](bool ok, int a, int b, unsigned esize) {
         return ok ? esize * ((unsigned)(y0 + b) * kp.nx + (x0 + a)) : kOOB;
     };
+    // the store offsets of the owned mu-, phi- and tile points, once per
+    // march (kOOB: not a point of the tile inside the grid)
+    unsigned omu[MM], ofp[MP];
+#pragma unroll
+    for (int m = 0; m < MM; ++m) {
+        const int r = tid + m * CB, a = r % WM, b = r / WM;
+        omu[m] = ioff(r < NM && a >= 3 && b >= 3 && a < TX + 3 && b < TY + 3 && interior(a - 3, b - 3), a - 3, b - 3, 8u);
+    }
+#pragma unroll
+    for (int m = 0; m < MP; ++m) {
+        const int r = tid + m * CB, a = r % WP, b = r / WP;
+        ofp[m] = ioff(r < NP && a >= 1 && b >= 1 && a <= TX && b <= TY && interior(a - 1, b - 1), a - 1, b - 1,
+                      (unsigned)sizeof(real));
+    }
+    const unsigned oq = ioff(interior(tid % TX, tid / TX), tid % TX, tid / TX, (unsigned)sizeof(real));
 
     // Global loads run ahead of their use: rho one iteration ahead, mu0 and
     // j issued right after the stage that consumed the previous plane.
@@ -253,10 +268,10 @@ __global__ __launch_bounds__(CB) void k_chain(KP kp, const double *__restrict__ 
                         const double s27 = A1 * Pr[m][0] + A0 * Pr[m][1] + A1 * Pr[m][2];
                         v = m0[m] - kp.kappa * 6.0 * (s27 - r0);
                         sm[p & 1][r] = v;
-                        out = out_plane && a >= 3 && b >= 3 && a < TX + 3 && b < TY + 3 && interior(a - 3, b - 3);
+                        out = out_plane;
                     }
                 }
-                bstore(v, rmu, ioff(out, a - 3, b - 3, 8u));
+                bstore(v, rmu, out ? omu[m] : kOOB);
             }
             issue_mu0(g3);
             if constexpr (WALLS) {
@@ -317,10 +332,10 @@ __global__ __launch_bounds__(CB) void k_chain(KP kp, const double *__restrict__ 
                         sp[0][r] = c2 * ux;
                         sp[1][r] = c2 * uy;
                         sp[2][r] = c2 * uz;
-                        out = out_plane && a >= 1 && b >= 1 && a <= TX && b <= TY && interior(a - 1, b - 1);
+                        out = out_plane;
                     }
                 }
-                const unsigned o = ioff(out, a - 1, b - 1, (unsigned)sizeof(real));
+                const unsigned o = out ? ofp[m] : kOOB;
                 bstore(Fx, rF0, o);
                 bstore(Fy, rF1, o);
                 bstore(Fz, rF2, o);
@@ -354,7 +369,7 @@ __global__ __launch_bounds__(CB) void k_chain(KP kp, const double *__restrict__ 
             {
                 const real h = (real)(-1.5);
                 const size_t base0 = pbase(g0);
-                const unsigned o = ioff(p0 >= zs && fluid(p0) && interior(a, b), a, b, (unsigned)sizeof(real));
+                const unsigned o = p0 >= zs && fluid(p0) ? oq : kOOB;
                 bstore(h * (w1r * Xr[0] + w0r * Xr[1] + w1r * Xr[2]), plane_rsrc(Q + base0, pbytesr), o);
                 bstore(h * (w1r * Yr[0] + w0r * Yr[1] + w1r * Yr[2]), plane_rsrc(Q + N + base0, pbytesr), o);
                 bstore(h * (Zr[2] - Zr[0]), plane_rsrc(Q + 2 * N + base0, pbytesr), o);
