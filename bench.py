@@ -683,14 +683,27 @@ def summarize_counters(fetch_csv, write_csv, form, workload_name, out_path):
     w_fac = gib_kib / max(max(write_all[k]) for k in copy_k if k in write_all)
     fetch = {k: sum(v) / len(v) for k, v in fetch_all.items()}
     write = {k: sum(v) / len(v) for k, v in write_all.items()}
+    launches = {k: len(v) for k, v in fetch_all.items()}
     res = {"form": form, "workload": workload_name, "source_hash": kernel_source_hash(),
            "dominant_kernel": re.sub(r"^void |lbfe::\(anonymous namespace\)::|\(lbfe::KP.*$", "", dom[0]),
            "fetch_kib_per_launch": fetch[dom[0]], "write_kib_per_launch": write[dom[0]],
            "copy_fetch_factor": f_fac, "copy_write_factor": w_fac,
            "bytes_per_launch": (fetch[dom[0]] * f_fac + write[dom[0]] * w_fac) * 1024.0,
-           "kernels": {"fetch_kib": fetch, "write_kib": write}}
+           "kernels": {"fetch_kib": fetch, "write_kib": write, "launches": launches}}
     json.dump(res, open(out_path, "w"), indent=1)
     print(json.dumps({k: v for k, v in res.items() if k != "kernels"}))
+
+
+def step_kernels(c):
+    """The kernels of one step in a counter summary: the step-path kernels
+    launched as often as the dominant kernel (once per step); kernels that
+    ran fewer times (the initial refresh of the moments, the initialiser)
+    are not part of a step."""
+    launches = c["kernels"]["launches"]
+    dom = [k for k in launches if re.sub(r"^void |lbfe::\(anonymous namespace\)::|\(lbfe::KP.*$", "", k)
+           == c["dominant_kernel"]]
+    n = launches[dom[0]]
+    return {k for k, m in launches.items() if m == n and any(s in k for s in STEP_KERNELS)}
 
 
 def summarize_adjoint_counters(fetch_csv, write_csv, out_path):
@@ -848,8 +861,9 @@ def main():
             # achieved HBM fraction of the whole step: calibrated counter
             # bytes of every kernel of one step over the measured step time
             ff, wf = c["copy_fetch_factor"], c["copy_write_factor"]
-            tb = sum(v * ff for k, v in c["kernels"]["fetch_kib"].items() if any(s in k for s in STEP_KERNELS))
-            tb += sum(v * wf for k, v in c["kernels"]["write_kib"].items() if any(s in k for s in STEP_KERNELS))
+            per_step = step_kernels(c)
+            tb = sum(v * ff for k, v in c["kernels"]["fetch_kib"].items() if k in per_step)
+            tb += sum(v * wf for k, v in c["kernels"]["write_kib"].items() if k in per_step)
             roof["step_traffic"] = tb * 1024.0
             roof["step_achieved_frac"] = round(tb * 1024.0 / (r["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     print("[bench] device copy bandwidth", file=sys.stderr, flush=True)

@@ -47,6 +47,10 @@ def test_counter_calibration(tmp_path):
     assert c["fetch_kib_per_launch"] == pytest.approx(1100.0)
     assert c["bytes_per_launch"] == pytest.approx((1100.0 * 2.0 + 500.0) * 1024.0)
     assert c["kernels"]["fetch_kib"]["k_moments<0>"] == pytest.approx(300.0)
+    # one step: the step-path kernels launched as often as the dominant one
+    # (k_moments ran once here, as the initial refresh of the fused path does)
+    assert c["kernels"]["launches"]["k_collide<0>"] == 2
+    assert bench.step_kernels(c) == {"k_collide<0>"}
     assert c["source_hash"] == bench.kernel_source_hash()
     assert (c["form"], c["workload"]) == ("fp64", "moving")
 
