@@ -91,3 +91,22 @@ def test_adjoint_counter_summary(tmp_path):
     finally:
         bench.ADJ_COUNTERS = saved
     assert adj["achieved_frac"] == pytest.approx(per_step_kib * 1024.0 / 0.5e-3 / 1e9 / bench.HBM_PEAK_GBS)
+
+
+def test_step_kernels_of_the_two_pass_path():
+    """On the two-pass path every step launches the moments, chain,
+    wall-density and collide-stream kernels once; the initialiser's kernels
+    ran once in the whole run and are not part of a step."""
+    n = 5
+    launches = {"k_moments<1>": n, "k_chain<1, true>": n, "k_wall_rho": n, "k_collide<1>": n,
+                "k_init<1>": 1, "k_mu": 1, "__amd_rocclr_copyBuffer": 7}
+    c = {"dominant_kernel": "k_collide<1>", "kernels": {"launches": launches}}
+    assert bench.step_kernels(c) == {"k_moments<1>", "k_chain<1, true>", "k_wall_rho", "k_collide<1>"}
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, bench.__file__, "--gpus", "2"], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
