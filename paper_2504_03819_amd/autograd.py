@@ -136,6 +136,7 @@ class LBFEFunction(torch.autograd.Function):
                 sim.step(min(K, cfg.steps - s))
         rho_T = sim.fields()["rho"]
         ctx.sim, ctx.cfg, ctx.checkpoints = sim, cfg, checkpoints
+        ctx.param_devices = (kappa.device, wet_value.device)
         ctx.save_for_backward(rho0)
         return rho_T
 
@@ -173,9 +174,10 @@ class LBFEFunction(torch.autograd.Function):
                 del states, recs
         g_rho0 = sim.adjoint_init_density(rho0.detach(), cfg.u0)
         g = sim.adjoint_grads()
-        dev = grad_rho.device
-        g_kappa = torch.tensor(g["kappa"], dtype=torch.float64, device=dev)
-        g_wet = torch.tensor(g["wet_value"], dtype=torch.float64, device=dev)
+        # each gradient on the device and in the dtype of its input
+        g_rho0 = g_rho0.to(device=rho0.device, dtype=rho0.dtype)
+        g_kappa = torch.tensor(g["kappa"], dtype=torch.float64, device=ctx.param_devices[0])
+        g_wet = torch.tensor(g["wet_value"], dtype=torch.float64, device=ctx.param_devices[1])
         cfg.stats["dL_dnu"] = g["nu"]
         ctx.sim = None
         ctx.checkpoints = None

@@ -161,6 +161,23 @@ def test_end_to_end_gradients_vs_oracle_and_fd(walls, wet_mode, wet_value, wall_
         assert abs(fd - float(g_r0[nd])) < 1e-5 * max(abs(fd), 1e-6)
 
 
+def test_gradients_come_back_on_the_input_devices():
+    """rho0, kappa and the wetting value may live on the host or on the GPU:
+    each gradient comes back on its input's device, with the same values."""
+    shape = (10, 8, 8)
+    rho0, tgt, cfg = _loss_setup(shape, True, 1, 1.3, 8)
+    out = {}
+    for dev in ("cpu", "cuda"):
+        r0 = torch.tensor(rho0, device=dev, requires_grad=True)
+        kap = torch.tensor(0.02, dtype=DT, device=dev, requires_grad=True)
+        wet = torch.tensor(1.3, dtype=DT, device=dev, requires_grad=True)
+        rT = lag.simulate(r0, kap, wet, cfg)
+        ((rT - torch.tensor(tgt, device=rT.device)) ** 2).sum().backward()
+        assert r0.grad.device.type == dev and kap.grad.device.type == dev and wet.grad.device.type == dev
+        out[dev] = (r0.grad.cpu(), float(kap.grad), float(wet.grad))
+    assert torch.equal(out["cpu"][0], out["cuda"][0]) and out["cpu"][1:] == out["cuda"][1:]
+
+
 def test_checkpoint_interval_does_not_change_gradients():
     """Uniform checkpoints every 1, 4, 9 steps (with and without the kept
     forward fields) and the binomial schedule with zero, one and two
