@@ -38,7 +38,27 @@ def build(verbose=False, extra=()):
     if verbose and r.stderr.strip():
         sys.stderr.write(r.stderr)
     os.replace(tmp, LIB)
+    build_c_example()
     return LIB
+
+
+C_EXAMPLE_SRC = os.path.join(ROOT, "tests", "c_abi_droplet.c")
+C_EXAMPLE = os.path.join(OUT_DIR, "c_abi_droplet")
+
+
+def build_c_example():
+    """The plain-C program of tests/c_abi_droplet.c against liblbfe.so and
+    the HIP runtime (gcc, no HIP device code), next to the library."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(rocm, "include"), C_EXAMPLE_SRC, "-o", C_EXAMPLE, "-L", OUT_DIR, "-llbfe",
+           "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-lm", "-Wl,-rpath,$ORIGIN",
+           "-Wl,-rpath," + os.path.join(rocm, "lib")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("gcc failed building the C ABI example")
+    return C_EXAMPLE
 
 
 if __name__ == "__main__":
